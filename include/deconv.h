@@ -1,0 +1,195 @@
+/*
+ * deconv.h -- C ABI of the MI355X partial-ADMM deconvolution library.
+ *
+ * The library runs the "partial ADMM" of Simoes, Almeida, Bioucas-Dias and
+ * Chanussot, "A Framework for Fast Image Deconvolution with Incomplete
+ * Observations" (arXiv 1602.01410), Sec. II-B, eqs. (admm_aprox_1)-(admm_aprox_4)
+ * with the closed forms (dual_x_iter_resolved_boundaries) and
+ * (dual_z_iter_resolved_boundaries) and the over-relaxed z-update that follows
+ * them, and the isotropic TV regulariser of Sec. III-B.
+ *
+ * Problem (Sec. I-A, model (4); Sec. II-A): the sharp image x lives on a
+ * periodic "extended" domain of height x width = m' x n' pixels.  The blurred
+ * image on that domain is H x (circular convolution with the (2b+1)^2 kernel h
+ * centred at the origin); only some of its pixels are observed:
+ *     y = M_y H x + n,
+ * and the others (z) are estimated along with x.  The method minimises
+ *     1/2 | [y; z] - H x |^2 + lambda sum_j sqrt((D_h x)_j^2 + (D_v x)_j^2)
+ * with one block-Gauss-Seidel pass (x-step then z-step) per ADMM iteration.
+ * The paper leaves several choices open; this library takes:
+ *   - D_h, D_v: periodic forward differences, x[i,j+1]-x[i,j], x[i+1,j]-x[i,j];
+ *   - vector soft threshold of u = D x^{i+1} + d^i with tau = lambda / mu
+ *     (|u| <= tau gives v = 0);
+ *   - z-update z <- z + alpha (M_z H x - z) (alpha = 2 is the paper's practice,
+ *     alpha = 1 the exact minimisation);
+ *   - initial state: observed pixels keep y, unobserved pixels inside the
+ *     central m x n region take the mean of the observed pixels, unobserved
+ *     pixels of the band of width b copy the nearest central pixel (Sec. III-B,
+ *     "repeating the border pixels"); x^0 = that image, v^0 = D x^0, d^0 = 0;
+ *   - the output x^N is the result of the N-th x-step.
+ *
+ * Memory: every pointer argument documented as "device" is HIP device memory
+ * owned by the caller; the library never frees or retains it beyond the call
+ * (except the workspace, retained for the plan's lifetime).  "host" pointers are
+ * read during the call only.  Execution is asynchronous on the plan's stream
+ * unless stated otherwise.  A plan is not thread-safe.
+ *
+ * Images of a batch are packed back to back: image b occupies
+ * height_b * width_b consecutive elements (row-major) starting at
+ * sum_{c<b} height_c * width_c.  Blur kernels are packed the same way with
+ * ksize_b^2 elements each.
+ *
+ * Supported sizes: every height and width must be 2^a * 3^c with c <= 2 and
+ * 8 <= size <= 2048 (DECONV_ERR_UNSUPPORTED_SIZE otherwise); ksize odd,
+ * 1 <= ksize, and 2 * (ksize / 2) < min(height, width).
+ *
+ * Errors: argument errors detected on the host return synchronously and leave
+ * the plan unchanged.  HIP errors return DECONV_ERR_HIP.  Non-finite residuals
+ * found on the device are reported in deconv_stats.status and by the next
+ * synchronising call.
+ */
+#ifndef DECONV_H
+#define DECONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DECONV_OK = 0,
+  DECONV_ERR_INVALID_ARG = 1,      /* null pointer, bad option, lambda < 0, mu <= 0, ... */
+  DECONV_ERR_UNSUPPORTED_SIZE = 2, /* length not 2^a 3^c (c <= 2) in [8, 2048], bad ksize */
+  DECONV_ERR_SINGULAR = 3,         /* sum(h) == 0: H^T H + mu D^T D singular at DC (Sec. III-B) */
+  DECONV_ERR_NONFINITE = 4,        /* NaN / Inf reached the residuals */
+  DECONV_ERR_NO_CHECKPOINTS = 5,   /* backward without a checkpointed forward run */
+  DECONV_ERR_HIP = 6,              /* a HIP runtime call failed */
+  DECONV_ERR_OOM = 7,              /* workspace too small / allocation failed */
+  DECONV_ERR_STATE = 8             /* call order violated (e.g. continue before run) */
+} deconv_status;
+
+enum {
+  DECONV_MASK_BOUNDARY = 0, /* unknown boundaries: only the central m x n region observed */
+  DECONV_MASK_EXPLICIT = 1, /* caller's byte mask over the whole extended grid (1 = observed) */
+  DECONV_MASK_DECIMATE = 2  /* boundary + super-resolution: central pixels (b+s*i, b+s*j) only */
+};
+
+typedef struct deconv_plan_s* deconv_plan; /* opaque */
+
+/* One image of a batch. */
+typedef struct {
+  int32_t height, width; /* m', n': the periodic extended domain (= sharp image size) */
+  int32_t ksize;         /* 2b+1: blur support, odd */
+  int32_t mask_kind;     /* DECONV_MASK_* */
+  int32_t decim;         /* s for DECONV_MASK_DECIMATE (>= 1), ignored otherwise */
+} deconv_image_desc;
+
+typedef struct {
+  float alpha;          /* z over-relaxation (default 2.0; must be in (0, 2]) */
+  int32_t check_every;  /* compute FP64 residuals every K iterations (0 = never) */
+  double tol_primal;    /* stop an image when |d'-d|/sqrt(2N) <= tol_primal ... */
+  double tol_dual;      /* ... and |v'-v|/sqrt(2N) <= tol_dual (0 = never stop) */
+  int32_t use_graph;    /* capture the iteration in a hipGraph (default 1) */
+  int32_t batched;      /* 1: one launch per phase for all images of a length
+                           (default); 0: one launch per image per phase */
+  int32_t ckpt_every;   /* keep the state every k iterations for the backward
+                           pass (0 = no backward support) */
+  int32_t max_iters;    /* upper bound on iters, sizes the checkpoint store */
+} deconv_options;
+
+typedef struct {
+  int32_t iters_done;   /* iterations applied to this image */
+  double r_primal;      /* |d' - d| at the last check (FP64) */
+  double r_dual;        /* |v' - v| at the last check */
+  double r_z;           /* |z' - z| at the last check */
+  int32_t status;       /* DECONV_OK or DECONV_ERR_NONFINITE */
+} deconv_stats;
+
+/* Fill *opt with the defaults above. */
+deconv_status deconv_options_default(deconv_options* opt);
+
+/* Bytes of device workspace a plan for this batch needs (host call).
+   desc: host array [batch]. */
+deconv_status deconv_plan_workspace_size(int32_t batch, const deconv_image_desc* desc,
+                                         const deconv_options* opt, size_t* bytes);
+
+/* Create a plan (host call; synchronous).  desc: host array [batch], copied.
+   opt: NULL for defaults.  stream: hipStream_t (NULL = default stream) on
+   which every later call runs.  workspace: device buffer of at least
+   deconv_plan_workspace_size bytes, owned by the caller and used until
+   deconv_plan_destroy; NULL makes the plan allocate (and free) its own. */
+deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, const deconv_image_desc* desc,
+                                 const deconv_options* opt, void* stream, void* workspace,
+                                 size_t workspace_bytes);
+
+deconv_status deconv_plan_destroy(deconv_plan p);
+
+/*
+ * Blur spectrum setup + initial state + `iters` partial-ADMM iterations.
+ *   y      device float, packed images: observed values (others ignored)
+ *   mask   device uint8, packed images, 1 = observed; read only for images of
+ *          kind DECONV_MASK_EXPLICIT (may be NULL if there are none)
+ *   h      device float, packed kernels (convolution, centre (b, b)); each
+ *          must have a non-zero sum (else DECONV_ERR_SINGULAR, checked on the
+ *          host after the spectrum is built; the call then synchronises)
+ *   lambda device float [batch], >= 0 (TV weight)
+ *   mu     device float [batch], > 0 (ADMM penalty)
+ *   iters  >= 1
+ *   x_out  device float, packed: x^iters on the whole extended domain
+ *   ytilde_out  device float, packed, nullable: [y; z] after the last z-step
+ *   stats  host array [batch], nullable; when given the call synchronises
+ *          and fills it.
+ * The state (ytilde, v, d) stays in the plan for deconv_admm_continue,
+ * deconv_state_export and, with checkpoints, deconv_admm_backward.
+ */
+deconv_status deconv_admm_run(deconv_plan p, const float* y, const uint8_t* mask, const float* h,
+                              const float* lambda, const float* mu, int32_t iters, float* x_out,
+                              float* ytilde_out, deconv_stats* stats);
+
+/* `iters` more iterations from the plan's current state (same lambda / mu
+   pointers as the run; read again).  Outputs as deconv_admm_run. */
+deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const float* mu,
+                                   int32_t iters, float* x_out, float* ytilde_out,
+                                   deconv_stats* stats);
+
+/* Copy the resumable state w = [z; v; d] (Appendix B) out of / into the plan.
+   ytilde: packed float (observed pixels hold y); v, d: packed float2 per
+   pixel (horizontal, vertical).  Import also needs h for the spectrum (device
+   float, packed) and makes deconv_admm_continue start from this state. */
+deconv_status deconv_state_export(deconv_plan p, float* ytilde, float* v, float* d);
+deconv_status deconv_state_import(deconv_plan p, const float* h, const float* mu,
+                                  const float* ytilde, const float* v, const float* d);
+
+/*
+ * Reverse mode through the last deconv_admm_run (which must have had
+ * opt.ckpt_every > 0 and iters <= opt.max_iters).  Inputs are those of that
+ * run; grad_x = dL/dx^N (device float, packed).  Outputs (device):
+ *   grad_y       packed float, dL/dy, zero at unobserved pixels
+ *   grad_lambda  float [batch]
+ *   grad_h       packed float [ksize_b^2 per image]
+ * Recomputes the forward iterations between checkpoints.
+ */
+deconv_status deconv_admm_backward(deconv_plan p, const float* y, const uint8_t* mask,
+                                   const float* h, const float* lambda, const float* mu,
+                                   const float* grad_x, float* grad_y, float* grad_lambda,
+                                   float* grad_h);
+
+/* Blur spectrum H^ = DFT2(h embedded circularly centred at the origin) for
+   every image (device float2 packed, full height x width per image); built with
+   the library's own FFT.  Synchronous. */
+deconv_status deconv_blur_spectrum(deconv_plan p, const float* h, float* spectrum_out);
+
+/* Batched 2-D complex DFT with the library's FFT (unnormalised; inverse = 1
+   uses exp(+2 pi i jk/n)).  data: device float2 [count][height][width],
+   transformed in place.  Same size rules as images.  Runs on `stream`. */
+deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* data,
+                          int32_t inverse, void* stream);
+
+const char* deconv_status_str(deconv_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DECONV_H */

@@ -1,0 +1,57 @@
+"""Build the HIP library (libdeconv.so) in-tree for gfx950.
+
+    python -m paper_1602_01410_amd.build
+
+Compiles csrc/deconv.hip (which includes the kernel headers) with hipcc into
+paper_1602_01410_amd/libdeconv.so.  Packed-FP32 instructions are disabled for
+all device code.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libdeconv.so")
+ARCH = os.environ.get("DECONV_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def sources():
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))
+            if f.endswith((".hip", ".hpp", ".inc"))] + [os.path.join(ROOT, "include", "deconv.h")]
+
+
+def build(verbose=False, jobs=None):
+    """Compile libdeconv.so.  Always recompiles (the caller decides when)."""
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-result", "-I" + os.path.join(ROOT, "include"),
+           os.path.join(CSRC, "deconv.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def is_stale():
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(s) > t for s in sources())
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print("built", LIB)
+    sys.exit(0)

@@ -1,0 +1,449 @@
+// Reverse mode through unrolled partial-ADMM iterations (not in the paper;
+// derived from the forward steps of Sec. II-B / III-B).
+//
+// Forward iteration i maps the state (ytilde^i, v^i, d^i) to
+//   x = A^{-1}(H^T ytilde + mu D^T (v - d)),  A = H^T H + mu D^T D,
+//   z' = z + alpha (M_z H x - z),  u = D x + d,  v' = S_tau(u),  d' = u - v'.
+// Given the adjoints (zb, vb, db) of the new state and xb_direct = dL/dx (only
+// for the output iterate), one reverse step is
+//   t  = vb - db,           ub = db + J_S(u)^T t,   lambda_b -= <u/|u|, t>/mu,
+//   xb = xb_direct + D^T ub + H^T (alpha M_z^T zb),
+//   rb = A^{-1} xb          (A is symmetric: the same spectral solve),
+//   y_b += (H rb) on observed pixels,
+//   zb <- (1 - alpha) zb + (H rb) on unobserved pixels,
+//   vb <- mu D rb,          db <- ub - mu D rb,
+// and the blur gradient collects, in the frequency domain, per frequency k
+//   S_k += conj(QB_k) X_k + conj(Y_k) RB_k - 2 conj(H_k) Re(conj(RB_k) X_k)
+// (QB = DFT(alpha M_z^T zb), X = DFT(x), Y = DFT(ytilde^i), RB = DFT(rb));
+// dL/dh[p] = Re(sum_k S_k exp(-2 pi i k.p / N)) / N at the kernel taps.
+//
+// The kernels mirror the forward ones: a column pass (spectral solve + S
+// accumulation) and a row pass that finishes reverse step i (inverse row DFT
+// -> rb, H rb) and starts reverse step i-1 (forward row DFT of
+// D^T ub + i alpha M_z^T zb), with one halo row on each side.
+#pragma once
+#include "kernels.hpp"
+
+namespace dcv {
+
+enum { BWD_ITER = 0, BWD_START = 1, BWD_END = 2 };
+
+struct BwdRowArgs {
+  const ImgMeta* meta;
+  const int4* tiles;
+  const float4* spec_in;   // (RB, H RB) column-pass output
+  float4* spec_out;        // (DFT_row(xb), DFT_row(qb)) for the next column pass
+  const float2* ub_in;     // ub of the step being finished (halo rows read)
+  float2* ub_out;          // ub of the step being started
+  float2* vb;              // adjoint state at segment boundaries
+  float2* db;
+  float* zb;               // adjoint of z (unobserved pixels)
+  float* yb;               // accumulated dL/dy (observed pixels)
+  const float2* u;         // u = D x + d of the forward step being started
+  const float* grad_x;     // dL/dx^N (first reverse step only), nullable
+  const uint8_t* mask;
+  const float* lam;
+  const float* mu;
+  const float2* tw;
+  double* lam_part;        // per row tile, accumulated dL/dlambda
+  float alpha;
+  int mode;
+};
+
+struct BwdColArgs {
+  const ImgMeta* meta;
+  const int4* tiles;
+  const float4* spec_in;
+  float4* spec_out;
+  const float2* hh;
+  const float* tab;
+  const float* mu;
+  const float2* tw;
+  const float4* fwd_spec;  // (Y, X / (m'n')) stored by the forward recompute
+  float2* S;               // accumulated spectral blur gradient (half, tiled)
+};
+
+// J^T t for the vector soft threshold at u (J is symmetric); also returns the
+// derivative of <S_tau(u), t> with respect to tau.
+__device__ __forceinline__ float2 vsoft_vjp(float2 u, float2 t, float tau, float& dtau) {
+  const float nr = sqrtf(u.x * u.x + u.y * u.y);
+  if (!(nr > tau)) { dtau = 0.f; return make_float2(0.f, 0.f); }
+  const float s = 1.f - tau / nr;
+  const float ut = (u.x * t.x + u.y * t.y);
+  const float c = ut * tau / (nr * nr * nr);
+  dtau = -ut / nr;
+  return make_float2(s * t.x + c * u.x, s * t.y + c * u.y);
+}
+
+template <int L>
+__device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r0, float2* lds) {
+  constexpr int RT = rt_for(L);
+  constexpr int LS = lstride(L);
+  constexpr int KP = ((RT + 1) * L + kNT - 1) / kNT;
+  const ImgMeta mt = a.meta[img];
+  const int M = mt.m;
+  const int nr = min(RT, M - r0);
+  const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
+  float2* buf = lds;
+  float2* tw = lds + (RT + 2) * LS;
+  load_twiddles<L, kNT>(tw, a.tw + mt.twr);
+  const float mu = a.mu[img];
+  const float tau = a.lam[img] / mu;
+  const int npx = (nr + 1) * L;
+  float2 ureg[KP];
+  float qreg[KP];
+  float lsum = 0.f;
+
+  if (a.mode != BWD_START) {
+    // finish reverse step: rb + i H rb on rows r0-1 .. r0+nr
+    const float4* __restrict__ sin = a.spec_in + mt.sp;
+    const int nl = nr + 2;
+    const int tot = nb * nl * C;
+    for (int q = threadIdx.x; q < tot; q += kNT) {
+      const int c = q & (C - 1);
+      const int t2 = q >> logC;
+      const int l = t2 % nl, blk = t2 / nl;
+      const int kx = blk * C + c;
+      if (kx >= nh) continue;
+      const int i = wrapi(r0 - 1 + l, M);
+      const float4 v = sin[((long long)blk * M + i) * C + c];
+      float2* line = buf + l * LS;
+      line[lpad(kx)] = make_float2(v.x - v.w, v.y + v.z);
+      if (kx >= 1 && kx <= L - nh) line[lpad(L - kx)] = make_float2(v.x + v.w, v.z - v.y);
+    }
+    __syncthreads();
+    fft_lines<L, true, kNT, RT + 2>(buf, nl, tw);
+  }
+
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      const int i = wrapi(r0 - 1 + l, M);
+      const long long pix = mt.px + (long long)i * L + j;
+      float2 vbv, dbv;
+      float hr = 0.f;
+      if (a.mode == BWD_START) {
+        vbv = a.vb[pix];
+        dbv = a.db[pix];
+      } else {
+        const float2 c0 = buf[l * LS + lpad(j)];
+        const float r = c0.x;
+        hr = c0.y;
+        const float rr = buf[l * LS + lpad(j + 1 == L ? 0 : j + 1)].x;
+        const float rd = buf[(l + 1) * LS + lpad(j)].x;
+        const float2 ubo = a.ub_in[pix];
+        vbv = make_float2(mu * (rr - r), mu * (rd - r));
+        dbv = make_float2(ubo.x - vbv.x, ubo.y - vbv.y);
+      }
+      float qb = 0.f;
+      if (l >= 1) {
+        const bool obs = observed(mt, a.mask, i, j);
+        if (a.mode == BWD_START) {
+          if (!obs) qb = a.alpha * a.zb[pix];
+        } else {
+          if (obs) {
+            a.yb[pix] += hr;
+          } else {
+            const float zn = (1.f - a.alpha) * a.zb[pix] + hr;
+            a.zb[pix] = zn;
+            qb = a.alpha * zn;
+          }
+          if (a.mode == BWD_END) { a.vb[pix] = vbv; a.db[pix] = dbv; }
+        }
+      }
+      if (a.mode != BWD_END) {
+        const float2 uu = a.u[pix];
+        const float2 t = make_float2(vbv.x - dbv.x, vbv.y - dbv.y);
+        float dt;
+        const float2 jt = vsoft_vjp(uu, t, tau, dt);
+        const float2 ub = make_float2(dbv.x + jt.x, dbv.y + jt.y);
+        ureg[k] = ub;
+        if (l >= 1) {
+          a.ub_out[pix] = ub;
+          lsum += dt;
+        }
+      }
+      qreg[k] = qb;
+    }
+  }
+
+  if (a.mode != BWD_END) {
+    __shared__ double red[3 * (kNT / 64)];
+    double ls = lsum, z0 = 0.0, z1 = 0.0;
+    block_sum3(ls, z0, z1, red);
+    if (threadIdx.x == 0) a.lam_part[mt.rt0 + r0 / RT] += ls / (double)mu;
+  } else {
+    return;
+  }
+
+  // start the next reverse step: xb = D^T ub (+ grad_x), qb, forward row DFT
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      buf[l * LS + lpad(j)] = ureg[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      if (l >= 1) {
+        const float2 w = buf[l * LS + lpad(j)];
+        const float whl = buf[l * LS + lpad(j == 0 ? L - 1 : j - 1)].x;
+        const float wvu = buf[(l - 1) * LS + lpad(j)].y;
+        float xb = whl - w.x + wvu - w.y;
+        if (a.grad_x) xb += a.grad_x[mt.px + (long long)(r0 - 1 + l) * L + j];
+        ureg[k] = make_float2(xb, qreg[k]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      if (l >= 1) buf[l * LS + lpad(j)] = ureg[k];
+    }
+  }
+  __syncthreads();
+  fft_lines<L, false, kNT, RT>(buf + LS, nr, tw);
+  float4* __restrict__ sout = a.spec_out + mt.sp;
+  const int tot2 = nb * nr * C;
+  for (int q = threadIdx.x; q < tot2; q += kNT) {
+    const int c = q & (C - 1);
+    const int t2 = q >> logC;
+    const int l = t2 % nr, blk = t2 / nr;
+    const int kx = blk * C + c;
+    if (kx >= nh) continue;
+    const float2 cf = buf[(l + 1) * LS + lpad(kx)];
+    const float2 cm = buf[(l + 1) * LS + lpad(kx == 0 ? 0 : L - kx)];
+    sout[((long long)blk * M + r0 + l) * C + c] =
+        make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kNT) bwd_row_kernel(BwdRowArgs a) {
+  extern __shared__ float2 lds[];
+  const int4 t = a.tiles[blockIdx.x];
+  bwd_row_tile<L>(a, t.x, t.y, lds);
+}
+
+template <int L>
+__device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int blk, float2* lds) {
+  constexpr int C = c_for(L);
+  constexpr int LS = lstride(L);
+  const ImgMeta mt = a.meta[img];
+  float2* buf = lds;
+  float2* tw = lds + 2 * C * LS;
+  load_twiddles<L, kNT>(tw, a.tw + mt.twc);
+  const long long base = mt.sp + (long long)blk * L * C;
+  const float4* __restrict__ sin = a.spec_in + base;
+  for (int q = threadIdx.x; q < L * C; q += kNT) {
+    const int i = q / C, c = q - i * C;
+    const float4 v = sin[q];
+    buf[(2 * c) * LS + lpad(i)] = make_float2(v.x, v.y);
+    buf[(2 * c + 1) * LS + lpad(i)] = make_float2(v.z, v.w);
+  }
+  __syncthreads();
+  fft_lines<L, false, kNT, 2 * C>(buf, 2 * C, tw);
+  const float mu = a.mu[img];
+  const float mn = (float)L * (float)mt.n;
+  const float scale = 1.0f / mn;
+  const float2* __restrict__ hh = a.hh + mt.hh + (long long)blk * L * C;
+  const float* __restrict__ dv2 = a.tab + mt.tab;
+  const float* __restrict__ dh2 = dv2 + L;
+  const float4* __restrict__ fs = a.fwd_spec + base;
+  float2* S = a.S + mt.hh + (long long)blk * L * C;
+  for (int q = threadIdx.x; q < L * C; q += kNT) {
+    const int ky = q / C, c = q - ky * C;
+    const int kx = blk * C + c;
+    const float2 XB = buf[(2 * c) * LS + lpad(ky)];
+    const float2 QB = buf[(2 * c + 1) * LS + lpad(ky)];
+    float2 R = make_float2(0.f, 0.f), HR = R;
+    if (kx < mt.nh) {
+      const float2 Hk = hh[q];
+      const float den = Hk.x * Hk.x + Hk.y * Hk.y + mu * (dh2[kx] + dv2[ky]);
+      // xb_hat = XB + conj(H) QB ; rb_hat = xb_hat / den
+      const float2 xbh = make_float2(XB.x + Hk.x * QB.x + Hk.y * QB.y, XB.y + Hk.x * QB.y - Hk.y * QB.x);
+      const float2 rb = make_float2(xbh.x / den, xbh.y / den);
+      const float4 f = fs[q];
+      const float2 Y = make_float2(f.x, f.y);
+      const float2 X = make_float2(f.z * mn, f.w * mn);
+      // conj(QB) X + conj(Y) rb - 2 conj(H) Re(conj(rb) X)
+      const float re = rb.x * X.x + rb.y * X.y;
+      float2 acc = S[q];
+      acc.x += QB.x * X.x + QB.y * X.y + Y.x * rb.x + Y.y * rb.y - 2.f * Hk.x * re;
+      acc.y += QB.x * X.y - QB.y * X.x + Y.x * rb.y - Y.y * rb.x + 2.f * Hk.y * re;
+      S[q] = acc;
+      R = make_float2(rb.x * scale, rb.y * scale);
+      HR = cmul(Hk, R);
+    }
+    buf[(2 * c) * LS + lpad(ky)] = R;
+    buf[(2 * c + 1) * LS + lpad(ky)] = HR;
+  }
+  __syncthreads();
+  fft_lines<L, true, kNT, 2 * C>(buf, 2 * C, tw);
+  float4* __restrict__ sout = a.spec_out + base;
+  for (int q = threadIdx.x; q < L * C; q += kNT) {
+    const int i = q / C, c = q - i * C;
+    const float2 X = buf[(2 * c) * LS + lpad(i)];
+    const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
+    sout[q] = make_float4(X.x, X.y, Q.x, Q.y);
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kNT) bwd_col_kernel(BwdColArgs a) {
+  extern __shared__ float2 lds[];
+  const int4 t = a.tiles[blockIdx.x];
+  bwd_col_tile<L>(a, t.x, t.y, lds);
+}
+
+// --------------------------------------------------------------------------
+// initialisation adjoint: ytilde^0 = E(y), v^0 = D ytilde^0, d^0 = 0
+// --------------------------------------------------------------------------
+
+// e = zb + D^T vb on unobserved pixels; observed pixels take D^T vb into yb
+__global__ void init_adj_a_kernel(const ImgMeta* meta, const uint8_t* __restrict__ mask, const float2* vb,
+                                  const float* zb, float* yb, float* e) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const long long n = (long long)mt.m * mt.n;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
+    const long long c = mt.px + p;
+    const float2 w = vb[c];
+    const float wl = vb[mt.px + (long long)i * mt.n + (j == 0 ? mt.n - 1 : j - 1)].x;
+    const float wu = vb[mt.px + (long long)(i == 0 ? mt.m - 1 : i - 1) * mt.n + j].y;
+    const float a = wl - w.x + wu - w.y;
+    if (observed(mt, mask, i, j)) { yb[c] += a; e[c] = 0.f; }
+    else e[c] = zb[c] + a;
+  }
+}
+
+// band pixels copy the nearest central pixel: gather their adjoints onto it;
+// then observed central pixels take it into yb, unobserved central pixels
+// add it to the adjoint of the mean (per-block partial)
+__global__ void __launch_bounds__(kNT) init_adj_b_kernel(const ImgMeta* meta, const uint8_t* __restrict__ mask,
+                                                         const float* e, float* yb, double* mean_part,
+                                                         int nblk) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const int b = mt.b, M = mt.m, N = mt.n;
+  const long long n = (long long)M * N;
+  double macc = 0.0;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / N), j = (int)(p - (long long)i * N);
+    if (!(i >= b && i < M - b && j >= b && j < N - b)) continue;
+    double s = e[mt.px + p];
+    const int i_lo = (i == b) ? 0 : i, i_hi = (i == M - b - 1) ? M - 1 : i;
+    const int j_lo = (j == b) ? 0 : j, j_hi = (j == N - b - 1) ? N - 1 : j;
+    if (i_lo != i_hi || j_lo != j_hi) {
+      for (int ii = i_lo; ii <= i_hi; ++ii)
+        for (int jj = j_lo; jj <= j_hi; ++jj) {
+          if (ii >= b && ii < M - b && jj >= b && jj < N - b) continue;   // central: not band
+          if (observed(mt, mask, ii, jj)) continue;
+          s += e[mt.px + (long long)ii * N + jj];
+        }
+    }
+    if (observed(mt, mask, i, j)) yb[mt.px + p] += (float)s;
+    else macc += s;
+  }
+  __shared__ double red[3 * (kNT / 64)];
+  double z0 = 0, z1 = 0;
+  block_sum3(macc, z0, z1, red);
+  if (threadIdx.x == 0) mean_part[(long long)img * nblk + blockIdx.x] = macc;
+}
+
+// observed pixels: + mean adjoint / count; unobserved: 0
+__global__ void __launch_bounds__(kNT) init_adj_c_kernel(const ImgMeta* meta, const uint8_t* __restrict__ mask,
+                                                         const double* mean_part, int nblk, const float* yb,
+                                                         float* grad_y) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const long long n = (long long)mt.m * mt.n;
+  __shared__ double tot[2];
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int k = 0; k < nblk; ++k) s += mean_part[(long long)img * nblk + k];
+    tot[0] = s;
+  }
+  // count observed pixels
+  double cnt = 0;
+  for (long long p = threadIdx.x; p < n; p += kNT) {
+    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
+    if (observed(mt, mask, i, j)) cnt += 1.0;
+  }
+  __shared__ double red[3 * (kNT / 64)];
+  double z0 = 0, z1 = 0;
+  block_sum3(cnt, z0, z1, red);
+  if (threadIdx.x == 0) tot[1] = cnt;
+  __syncthreads();
+  const float add = tot[1] > 0 ? (float)(tot[0] / tot[1]) : 0.f;
+  for (long long p = threadIdx.x; p < n; p += kNT) {
+    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
+    grad_y[mt.px + p] = observed(mt, mask, i, j) ? yb[mt.px + p] + add : 0.f;
+  }
+}
+
+// Hermitian completion of the accumulated half spectrum S into a full
+// complex m' x n' grid (for the final transform to the kernel taps)
+__global__ void unpack_half_kernel(const ImgMeta* meta, const float2* __restrict__ S, float2* grid,
+                                   const long long* goff) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const long long n = (long long)mt.m * mt.n;
+  float2* g = grid + goff[img];
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int ky = (int)(p / mt.n), kx = (int)(p - (long long)ky * mt.n);
+    float2 v;
+    if (kx < mt.nh) {
+      v = S[mt.hh + ((long long)(kx / mt.C) * mt.m + ky) * mt.C + kx % mt.C];
+    } else {
+      const int kx2 = mt.n - kx, ky2 = ky == 0 ? 0 : mt.m - ky;
+      const float2 w = S[mt.hh + ((long long)(kx2 / mt.C) * mt.m + ky2) * mt.C + kx2 % mt.C];
+      v = make_float2(w.x, -w.y);
+    }
+    g[p] = v;
+  }
+}
+
+// dL/dh[b+p][b+q] = Re(F(S))[p mod m', q mod n'] / (m' n')
+__global__ void gather_taps_kernel(const ImgMeta* meta, const float2* grid, const long long* goff,
+                                   const long long* hoff, float* grad_h) {
+  const int img = blockIdx.x;
+  const ImgMeta mt = meta[img];
+  const int K = 2 * mt.b + 1;
+  const float2* g = grid + goff[img];
+  const float inv = 1.0f / ((float)mt.m * (float)mt.n);
+  for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
+    const int pp = t / K - mt.b, qq = t % K - mt.b;
+    const int i = ((pp % mt.m) + mt.m) % mt.m, j = ((qq % mt.n) + mt.n) % mt.n;
+    grad_h[hoff[img] + t] = g[(long long)i * mt.n + j].x * inv;
+  }
+}
+
+// per image: sum of the per-tile dL/dlambda partials
+__global__ void __launch_bounds__(kNT) lam_reduce_kernel(const ImgMeta* meta, const double* part, float* out) {
+  const int img = blockIdx.x;
+  const ImgMeta mt = meta[img];
+  double a = 0, z0 = 0, z1 = 0;
+  for (int t = threadIdx.x; t < mt.nrt; t += kNT) a += part[mt.rt0 + t];
+  __shared__ double red[3 * (kNT / 64)];
+  block_sum3(a, z0, z1, red);
+  if (threadIdx.x == 0) out[img] = (float)a;
+}
+
+}  // namespace dcv

@@ -1,0 +1,941 @@
+// Host side of the partial-ADMM library: plans, workspace layout, launch
+// schedule and the C ABI declared in include/deconv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+#include <cstdint>
+
+#include "../../include/deconv.h"
+#include "kernels.hpp"
+#include "backward.hpp"
+
+using namespace dcv;
+
+// every supported line length: 2^a 3^c, a >= 1, c <= 2, 8 <= L <= 2048
+#define DCV_FOR_EACH_LEN(X)                                                                    \
+  X(8) X(12) X(16) X(18) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(128) X(144) X(192)   \
+  X(256) X(288) X(384) X(512) X(576) X(768) X(1024) X(1152) X(1536) X(2048)
+
+static bool supported_len(int L) {
+  switch (L) {
+#define DCV_CASE(n) case n: return true;
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return false;
+}
+
+#define HIPCHK(expr)                                                      \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      fprintf(stderr, "deconv: %s failed: %s (%s:%d)\n", #expr,           \
+              hipGetErrorString(e_), __FILE__, __LINE__);                 \
+      return DECONV_ERR_HIP;                                              \
+    }                                                                     \
+  } while (0)
+
+#define STCHK(expr)                                \
+  do {                                             \
+    deconv_status s_ = (expr);                     \
+    if (s_ != DECONV_OK) return s_;                \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel dispatch by compile-time length
+// ---------------------------------------------------------------------------
+static size_t row_lds_bytes(int L) {
+  size_t e = 0;
+  switch (L) {
+#define DCV_CASE(n) case n: e = row_lds_elems(n); break;
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return e * sizeof(float2);
+}
+static size_t col_lds_bytes(int L) {
+  size_t e = 0;
+  switch (L) {
+#define DCV_CASE(n) case n: e = col_lds_elems(n); break;
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return e * sizeof(float2);
+}
+
+template <typename K>
+static hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void** args) {
+  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(kNT), args, lds, s);
+}
+
+static hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a) {
+  void* args[] = {&a};
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(row_kernel<n>, grid, lds, s, args);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+static hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a) {
+  void* args[] = {&a};
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(col_kernel<n>, grid, lds, s, args);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+static hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a) {
+  void* args[] = {&a};
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(bwd_row_kernel<n>, grid, lds, s, args);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+static hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a) {
+  void* args[] = {&a};
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(bwd_col_kernel<n>, grid, lds, s, args);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+static size_t fftrow_lds_bytes(int L) {
+  int lpw = std::max(1, std::min(32, 4096 / L));
+  return (size_t)(lpw * lstride(L) + L) * sizeof(float2);
+}
+static size_t fftcol_lds_bytes(int L) { return (size_t)(2 * c_for(L) * lstride(L) + L) * sizeof(float2); }
+
+static hipError_t launch_fft_rows(int L, float2* data, long long nrows, const float2* tw, int inverse,
+                                  hipStream_t s) {
+  int lpw = std::max(1, std::min(32, 4096 / L));
+  int grid = (int)((nrows + lpw - 1) / lpw);
+  void* args[] = {&data, &nrows, &tw, &inverse};
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(fft_rows_kernel<n>, grid, fftrow_lds_bytes(n), s, args);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+static hipError_t launch_fft_cols(int L, float2* data, int W, int count, const float2* tw, int inverse,
+                                  hipStream_t s) {
+  int cw = 2 * c_for(L);
+  int grid = count * ((W + cw - 1) / cw);
+  void* args[] = {&data, &W, &count, &tw, &inverse};
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(fft_cols_kernel<n>, grid, fftcol_lds_bytes(n), s, args);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// LDS available to one workgroup; without a device (host-only checks) assume
+// the 160 KiB of gfx950, the only target this library is built for
+static int max_lds_bytes() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 163840;
+    v = (int)p.sharedMemPerBlock;
+  }
+  return v;
+}
+
+// twiddle tables exp(-2 pi i t / L), computed in double, stored as float
+static void twiddles(int L, std::vector<float2>& out) {
+  out.resize(L);
+  for (int t = 0; t < L; ++t) {
+    double a = -2.0 * M_PI * (double)t / (double)L;
+    out[t] = make_float2((float)cos(a), (float)sin(a));
+  }
+}
+
+// process-wide twiddle cache for the diagnostic FFT entry point (per device)
+static std::mutex g_tw_mu;
+static std::map<std::pair<int, int>, float2*> g_tw;
+static const float2* cached_twiddles(int L) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  auto key = std::make_pair(dev, L);
+  auto it = g_tw.find(key);
+  if (it != g_tw.end()) return it->second;
+  std::vector<float2> h;
+  twiddles(L, h);
+  float2* d = nullptr;
+  if (hipMalloc(&d, sizeof(float2) * L) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, h.data(), sizeof(float2) * L, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  g_tw[key] = d;
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct Group {
+  int L;
+  long long tile0;  // first tile in the tile table
+  int ntiles;
+  size_t lds;
+};
+
+struct deconv_plan_s {
+  int batch = 0;
+  std::vector<deconv_image_desc> desc;
+  deconv_options opt{};
+  hipStream_t stream = nullptr;     // the caller's stream: every call runs here
+  hipStream_t cap_stream = nullptr; // private stream, used only to capture graphs
+  hipStream_t ls = nullptr;         // stream the launch helpers enqueue on
+  std::vector<ImgMeta> meta;
+
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+
+  // device views into the workspace
+  ImgMeta* d_meta = nullptr;
+  int4* d_tiles = nullptr;
+  float* yt = nullptr;
+  float2* dbuf[2] = {nullptr, nullptr};
+  float2* v = nullptr;
+  float4* specA = nullptr;
+  float4* specB = nullptr;
+  float2* hh = nullptr;
+  float* tab = nullptr;
+  float2* tw = nullptr;
+  double* partials = nullptr;
+  int* done = nullptr;
+  int* nonfinite = nullptr;
+  int* iters_done = nullptr;
+  double* res = nullptr;
+  double* mean = nullptr;
+  long long* goff = nullptr;
+  long long* hoff = nullptr;
+  float2* hsum = nullptr;     // DC term of each spectrum (host check)
+  // backward support
+  float* ck_yt = nullptr;     // checkpoints: ytilde, v, d per stored iteration
+  float2* ck_v = nullptr;
+  float2* ck_d = nullptr;
+  float2* seg_u = nullptr;    // per iteration of a segment: u = D x + d
+  float4* seg_spec = nullptr; // per iteration of a segment: (Y, X) half spectra
+  float2* adj_a = nullptr;    // backward: ub ping-pong
+  float2* adj_b = nullptr;
+  float2* adj_vb = nullptr;   // backward: adjoint state at segment boundaries
+  float2* adj_db = nullptr;
+  double* adj_mean = nullptr; // backward: per-block partials of the mean adjoint
+  float* adj_z = nullptr;
+  float* adj_y = nullptr;
+  float2* adj_S = nullptr;    // accumulated spectral h-gradient (half, tiled)
+  double* adj_lam = nullptr;  // per row tile partial of dL/dlambda
+  int nck = 0;                // checkpoints stored
+
+  long long total_px = 0, total_sp = 0, total_hh = 0, total_tab = 0, total_tw = 0, total_rt = 0;
+  long long total_h = 0;      // packed blur kernel elements
+  std::vector<long long> hoff_h;
+  std::map<int, long long> tw_off;
+  std::vector<Group> row_groups, col_groups;
+  std::vector<std::vector<Group>> row_img, col_img;  // per-image launches (batched = 0)
+
+  int cur_d = 0;        // index of the d buffer holding the current state
+  bool have_state = false;
+  int last_iters = 0;   // iterations of the last run (for the backward)
+  bool ck_valid = false;
+
+  // graph cache: one executable graph per (check period, buffer parity,
+  // argument pointers); replayed for every whole check period of a run
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+};
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
+      off_part, off_done, off_nonf, off_itd, off_res, off_mean, off_goff, off_hoff, off_hsum;
+  size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
+      off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean;
+  size_t total;
+};
+
+static deconv_status validate(int32_t batch, const deconv_image_desc* desc, const deconv_options* opt) {
+  if (batch <= 0 || !desc) return DECONV_ERR_INVALID_ARG;
+  if (opt) {
+    if (!(opt->alpha > 0.f && opt->alpha <= 2.f)) return DECONV_ERR_INVALID_ARG;
+    if (opt->check_every < 0 || opt->ckpt_every < 0 || opt->max_iters < 0) return DECONV_ERR_INVALID_ARG;
+    if (opt->tol_primal < 0 || opt->tol_dual < 0) return DECONV_ERR_INVALID_ARG;
+    if (opt->ckpt_every > 0 && opt->max_iters <= 0) return DECONV_ERR_INVALID_ARG;
+    // the reverse pass replays every iteration: no early stopping with it
+    if (opt->ckpt_every > 0 && (opt->tol_primal > 0 || opt->tol_dual > 0)) return DECONV_ERR_INVALID_ARG;
+  }
+  for (int b = 0; b < batch; ++b) {
+    const deconv_image_desc& d = desc[b];
+    if (!supported_len(d.height) || !supported_len(d.width)) return DECONV_ERR_UNSUPPORTED_SIZE;
+    if (d.ksize < 1 || d.ksize % 2 == 0) return DECONV_ERR_UNSUPPORTED_SIZE;
+    if (2 * (d.ksize / 2) >= std::min(d.height, d.width)) return DECONV_ERR_UNSUPPORTED_SIZE;
+    if (d.mask_kind < 0 || d.mask_kind > 2) return DECONV_ERR_INVALID_ARG;
+    if (d.mask_kind == DECONV_MASK_DECIMATE && d.decim < 1) return DECONV_ERR_INVALID_ARG;
+    if ((int)row_lds_bytes(d.width) > max_lds_bytes() || (int)col_lds_bytes(d.height) > max_lds_bytes())
+      return DECONV_ERR_UNSUPPORTED_SIZE;
+  }
+  return DECONV_OK;
+}
+
+// build per-image metadata and the workspace layout
+static void build_layout(deconv_plan_s* p, Layout& lay) {
+  const int B = p->batch;
+  p->meta.assign(B, ImgMeta{});
+  p->hoff_h.assign(B, 0);
+  long long px = 0, sp = 0, hhp = 0, tab = 0, rt = 0, hk = 0;
+  std::map<int, long long> twoff;
+  long long tw = 0;
+  for (int b = 0; b < B; ++b) {
+    const deconv_image_desc& d = p->desc[b];
+    ImgMeta& m = p->meta[b];
+    m.m = d.height; m.n = d.width; m.b = d.ksize / 2;
+    m.mask_kind = d.mask_kind; m.decim = d.mask_kind == DECONV_MASK_DECIMATE ? d.decim : 1;
+    m.nh = d.width / 2 + 1;
+    m.C = c_for(d.height);
+    m.logC = 0; while ((1 << m.logC) < m.C) ++m.logC;
+    m.nb = (m.nh + m.C - 1) / m.C;
+    m.rt = rt_for(d.width);
+    m.nrt = (d.height + m.rt - 1) / m.rt;
+    m.px = px; m.sp = sp; m.hh = hhp; m.tab = tab; m.rt0 = rt;
+    for (int L : {d.width, d.height})
+      if (!twoff.count(L)) { twoff[L] = tw; tw += L; }
+    m.twr = twoff[d.width]; m.twc = twoff[d.height];
+    p->hoff_h[b] = hk;
+    px += (long long)d.height * d.width;
+    sp += (long long)d.height * m.nb * m.C;
+    hhp += (long long)d.height * m.nb * m.C;
+    tab += d.height + m.nb * m.C;
+    rt += m.nrt;
+    hk += (long long)d.ksize * d.ksize;
+  }
+  p->total_px = px; p->total_sp = sp; p->total_hh = hhp; p->total_tab = tab; p->total_tw = tw;
+  p->total_rt = rt; p->total_h = hk; p->tw_off = twoff;
+
+  // tiles: grouped by length, images contiguous inside a group
+  long long ntiles = 0;
+  p->row_groups.clear(); p->col_groups.clear();
+  p->row_img.assign(B, {}); p->col_img.assign(B, {});
+  std::map<int, std::vector<int>> by_w, by_h;
+  for (int b = 0; b < B; ++b) { by_w[p->desc[b].width].push_back(b); by_h[p->desc[b].height].push_back(b); }
+  for (auto& kv : by_w) {
+    Group g{kv.first, ntiles, 0, row_lds_bytes(kv.first)};
+    for (int b : kv.second) {
+      p->row_img[b].push_back(Group{kv.first, ntiles, p->meta[b].nrt, g.lds});
+      g.ntiles += p->meta[b].nrt;
+      ntiles += p->meta[b].nrt;
+    }
+    p->row_groups.push_back(g);
+  }
+  for (auto& kv : by_h) {
+    Group g{kv.first, ntiles, 0, col_lds_bytes(kv.first)};
+    for (int b : kv.second) {
+      p->col_img[b].push_back(Group{kv.first, ntiles, p->meta[b].nb, g.lds});
+      g.ntiles += p->meta[b].nb;
+      ntiles += p->meta[b].nb;
+    }
+    p->col_groups.push_back(g);
+  }
+
+  const size_t A = 256;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1), A); return r; };
+  lay.off_meta = take(sizeof(ImgMeta) * B);
+  lay.off_tiles = take(sizeof(int4) * ntiles);
+  lay.off_yt = take(sizeof(float) * px);
+  lay.off_d0 = take(sizeof(float2) * px);
+  lay.off_d1 = take(sizeof(float2) * px);
+  lay.off_v = take(sizeof(float2) * px);
+  lay.off_specA = take(sizeof(float4) * sp);
+  lay.off_specB = take(sizeof(float4) * sp);
+  lay.off_hh = take(sizeof(float2) * hhp);
+  lay.off_tab = take(sizeof(float) * tab);
+  lay.off_tw = take(sizeof(float2) * tw);
+  lay.off_part = take(sizeof(double) * 3 * rt);
+  lay.off_done = take(sizeof(int) * B);
+  lay.off_nonf = take(sizeof(int) * B);
+  lay.off_itd = take(sizeof(int) * B);
+  lay.off_res = take(sizeof(double) * 3 * B);
+  lay.off_mean = take(sizeof(double) * B);
+  lay.off_goff = take(sizeof(long long) * B);
+  lay.off_hoff = take(sizeof(long long) * B);
+  lay.off_hsum = take(sizeof(float2) * B);
+  const int ck = p->opt.ckpt_every;
+  if (ck > 0) {
+    const int nck = (p->opt.max_iters + ck - 1) / ck + 1;
+    lay.off_ck_yt = take(sizeof(float) * px * nck);
+    lay.off_ck_v = take(sizeof(float2) * px * nck);
+    lay.off_ck_d = take(sizeof(float2) * px * nck);
+    lay.off_seg_u = take(sizeof(float2) * px * ck);
+    lay.off_seg_spec = take(sizeof(float4) * sp * ck);
+    lay.off_adj_a = take(sizeof(float2) * px);
+    lay.off_adj_b = take(sizeof(float2) * px);
+    lay.off_adj_z = take(sizeof(float) * px);
+    lay.off_adj_y = take(sizeof(float) * px);
+    lay.off_adj_S = take(sizeof(float2) * hhp);
+    lay.off_adj_lam = take(sizeof(double) * rt);
+    lay.off_adj_vb = take(sizeof(float2) * px);
+    lay.off_adj_db = take(sizeof(float2) * px);
+    lay.off_adj_mean = take(sizeof(double) * 64 * B);
+  } else {
+    lay.off_ck_yt = lay.off_ck_v = lay.off_ck_d = lay.off_seg_u = lay.off_seg_spec = 0;
+    lay.off_adj_a = lay.off_adj_b = lay.off_adj_z = lay.off_adj_y = lay.off_adj_S = lay.off_adj_lam = 0;
+    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = 0;
+  }
+  lay.total = o;
+}
+
+template <typename T>
+static T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+extern "C" deconv_status deconv_options_default(deconv_options* opt) {
+  if (!opt) return DECONV_ERR_INVALID_ARG;
+  opt->alpha = 2.0f;
+  opt->check_every = 0;
+  opt->tol_primal = 0.0;
+  opt->tol_dual = 0.0;
+  opt->use_graph = 1;
+  opt->batched = 1;
+  opt->ckpt_every = 0;
+  opt->max_iters = 0;
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_workspace_size(int32_t batch, const deconv_image_desc* desc,
+                                                    const deconv_options* opt, size_t* bytes) {
+  if (!bytes) return DECONV_ERR_INVALID_ARG;
+  STCHK(validate(batch, desc, opt));
+  deconv_plan_s tmp;
+  tmp.batch = batch;
+  tmp.desc.assign(desc, desc + batch);
+  if (opt) tmp.opt = *opt; else deconv_options_default(&tmp.opt);
+  Layout lay;
+  build_layout(&tmp, lay);
+  *bytes = lay.total;
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
+  if (!p) return DECONV_ERR_INVALID_ARG;
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->own_ws && p->ws) (void)hipFree(p->ws);
+  delete p;
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, const deconv_image_desc* desc,
+                                            const deconv_options* opt, void* stream, void* workspace,
+                                            size_t workspace_bytes) {
+  if (!out) return DECONV_ERR_INVALID_ARG;
+  *out = nullptr;
+  STCHK(validate(batch, desc, opt));
+  deconv_plan_s* p = new (std::nothrow) deconv_plan_s;
+  if (!p) return DECONV_ERR_OOM;
+  p->batch = batch;
+  p->desc.assign(desc, desc + batch);
+  if (opt) p->opt = *opt; else deconv_options_default(&p->opt);
+  p->stream = static_cast<hipStream_t>(stream);
+  p->ls = p->stream;
+  if (p->opt.use_graph && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete p;
+    return DECONV_ERR_HIP;
+  }
+  Layout lay;
+  build_layout(p, lay);
+  if (workspace) {
+    if (workspace_bytes < lay.total) { delete p; return DECONV_ERR_OOM; }
+    p->ws = workspace;
+  } else {
+    if (hipMalloc(&p->ws, lay.total) != hipSuccess) { delete p; return DECONV_ERR_OOM; }
+    p->own_ws = true;
+  }
+  p->ws_bytes = lay.total;
+  void* w = p->ws;
+  p->d_meta = at<ImgMeta>(w, lay.off_meta);
+  p->d_tiles = at<int4>(w, lay.off_tiles);
+  p->yt = at<float>(w, lay.off_yt);
+  p->dbuf[0] = at<float2>(w, lay.off_d0);
+  p->dbuf[1] = at<float2>(w, lay.off_d1);
+  p->v = at<float2>(w, lay.off_v);
+  p->specA = at<float4>(w, lay.off_specA);
+  p->specB = at<float4>(w, lay.off_specB);
+  p->hh = at<float2>(w, lay.off_hh);
+  p->tab = at<float>(w, lay.off_tab);
+  p->tw = at<float2>(w, lay.off_tw);
+  p->partials = at<double>(w, lay.off_part);
+  p->done = at<int>(w, lay.off_done);
+  p->nonfinite = at<int>(w, lay.off_nonf);
+  p->iters_done = at<int>(w, lay.off_itd);
+  p->res = at<double>(w, lay.off_res);
+  p->mean = at<double>(w, lay.off_mean);
+  p->goff = at<long long>(w, lay.off_goff);
+  p->hoff = at<long long>(w, lay.off_hoff);
+  p->hsum = at<float2>(w, lay.off_hsum);
+  if (p->opt.ckpt_every > 0) {
+    p->ck_yt = at<float>(w, lay.off_ck_yt);
+    p->ck_v = at<float2>(w, lay.off_ck_v);
+    p->ck_d = at<float2>(w, lay.off_ck_d);
+    p->seg_u = at<float2>(w, lay.off_seg_u);
+    p->seg_spec = at<float4>(w, lay.off_seg_spec);
+    p->adj_a = at<float2>(w, lay.off_adj_a);
+    p->adj_b = at<float2>(w, lay.off_adj_b);
+    p->adj_z = at<float>(w, lay.off_adj_z);
+    p->adj_y = at<float>(w, lay.off_adj_y);
+    p->adj_S = at<float2>(w, lay.off_adj_S);
+    p->adj_lam = at<double>(w, lay.off_adj_lam);
+    p->adj_vb = at<float2>(w, lay.off_adj_vb);
+    p->adj_db = at<float2>(w, lay.off_adj_db);
+    p->adj_mean = at<double>(w, lay.off_adj_mean);
+  }
+
+  // host-built tables
+  std::vector<int4> tiles;
+  for (auto& g : p->row_groups)
+    for (int b = 0; b < batch; ++b)
+      if (p->desc[b].width == g.L)
+        for (int t = 0; t < p->meta[b].nrt; ++t) tiles.push_back(make_int4(b, t * p->meta[b].rt, 0, 0));
+  for (auto& g : p->col_groups)
+    for (int b = 0; b < batch; ++b)
+      if (p->desc[b].height == g.L)
+        for (int t = 0; t < p->meta[b].nb; ++t) tiles.push_back(make_int4(b, t, 0, 0));
+  std::vector<float2> tw(p->total_tw);
+  for (auto& kv : p->tw_off) {
+    std::vector<float2> t;
+    twiddles(kv.first, t);
+    std::copy(t.begin(), t.end(), tw.begin() + kv.second);
+  }
+  std::vector<float> tab(p->total_tab);
+  std::vector<long long> goff(batch), hoff(batch);
+  for (int b = 0; b < batch; ++b) {
+    const ImgMeta& m = p->meta[b];
+    for (int k = 0; k < m.m; ++k) {
+      double s = sin(M_PI * (double)k / (double)m.m);
+      tab[m.tab + k] = (float)(4.0 * s * s);
+    }
+    for (int k = 0; k < m.nb * m.C; ++k) {
+      double s = sin(M_PI * (double)k / (double)m.n);
+      tab[m.tab + m.m + k] = (float)(4.0 * s * s);
+    }
+    goff[b] = 2 * m.sp;  // the setup grid (float2 units) lives in specB
+    hoff[b] = p->hoff_h[b];
+  }
+  hipStream_t s = p->stream;
+  auto fail = [&](deconv_status st) { deconv_plan_destroy(p); return st; };
+  if (hipMemcpyAsync(p->d_meta, p->meta.data(), sizeof(ImgMeta) * batch, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(p->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(p->tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(p->tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(p->goff, goff.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(p->hoff, hoff.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s) != hipSuccess ||
+      // padded spectrum entries are never written by the passes: clear once
+      hipMemsetAsync(p->specA, 0, sizeof(float4) * p->total_sp, s) != hipSuccess ||
+      hipMemsetAsync(p->specB, 0, sizeof(float4) * p->total_sp, s) != hipSuccess ||
+      hipMemsetAsync(p->done, 0, sizeof(int) * batch, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(DECONV_ERR_HIP);
+  *out = p;
+  return DECONV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// run
+// ---------------------------------------------------------------------------
+static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out) {
+  hipStream_t s = p->stream;
+  float2* grid = reinterpret_cast<float2*>(p->specB);
+  const int B = p->batch;
+  int gx = 64;
+  hipLaunchKernelGGL(embed_psf_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, grid, p->goff);
+  HIPCHK(hipGetLastError());
+  for (int b = 0; b < B; ++b) {
+    const ImgMeta& m = p->meta[b];
+    float2* g = grid + 2 * m.sp;
+    HIPCHK(launch_fft_rows(m.n, g, m.m, p->tw + m.twr, 0, s));
+    HIPCHK(launch_fft_cols(m.m, g, m.n, 1, p->tw + m.twc, 0, s));
+    if (full_out)
+      HIPCHK(hipMemcpyAsync(reinterpret_cast<float2*>(full_out) + m.px, g, sizeof(float2) * m.m * m.n,
+                            hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->hsum + b, g, sizeof(float2), hipMemcpyDeviceToDevice, s));
+  }
+  hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
+  HIPCHK(hipGetLastError());
+  std::vector<float2> hs(B);
+  HIPCHK(hipMemcpyAsync(hs.data(), p->hsum, sizeof(float2) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b)
+    if (!(std::isfinite(hs[b].x) && std::isfinite(hs[b].y)) || (hs[b].x == 0.f && hs[b].y == 0.f))
+      return DECONV_ERR_SINGULAR;
+  return DECONV_OK;
+}
+
+static RowArgs row_args(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu) {
+  RowArgs a{};
+  a.meta = p->d_meta;
+  a.tiles = p->d_tiles;
+  a.spec_in = p->specB;
+  a.spec_out = p->specA;
+  a.yt = p->yt;
+  a.v = p->v;
+  a.mask = mask;
+  a.lam = lam;
+  a.mu = mu;
+  a.tw = p->tw;
+  a.partials = p->partials;
+  a.done = p->done;
+  a.alpha = p->opt.alpha;
+  return a;
+}
+
+static ColArgs col_args(deconv_plan_s* p, const float* mu) {
+  ColArgs a{};
+  a.meta = p->d_meta;
+  a.tiles = p->d_tiles;
+  a.spec_in = p->specA;
+  a.spec_out = p->specB;
+  a.hh = p->hh;
+  a.tab = p->tab;
+  a.mu = mu;
+  a.tw = p->tw;
+  a.done = p->done;
+  return a;
+}
+
+// launch the row pass over every image (batched) or image by image
+static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
+  if (p->opt.batched) {
+    for (auto& g : p->row_groups) {
+      a.tiles = p->d_tiles + g.tile0;
+      HIPCHK(launch_row(g.L, g.ntiles, g.lds, p->ls, a));
+    }
+  } else {
+    for (int b = 0; b < p->batch; ++b)
+      for (auto& g : p->row_img[b]) {
+        a.tiles = p->d_tiles + g.tile0;
+        HIPCHK(launch_row(g.L, g.ntiles, g.lds, p->ls, a));
+      }
+  }
+  return DECONV_OK;
+}
+
+static deconv_status launch_cols(deconv_plan_s* p, ColArgs a) {
+  if (p->opt.batched) {
+    for (auto& g : p->col_groups) {
+      a.tiles = p->d_tiles + g.tile0;
+      HIPCHK(launch_col(g.L, g.ntiles, g.lds, p->ls, a));
+    }
+  } else {
+    for (int b = 0; b < p->batch; ++b)
+      for (auto& g : p->col_img[b]) {
+        a.tiles = p->d_tiles + g.tile0;
+        HIPCHK(launch_col(g.L, g.ntiles, g.lds, p->ls, a));
+      }
+  }
+  return DECONV_OK;
+}
+
+// first spectra from the stored state (ytilde, v, d = dbuf[cur_d])
+static deconv_status prologue_from_state(deconv_plan_s* p, const float* mu) {
+  RowArgs a = row_args(p, nullptr, mu, mu);
+  a.mode = ROW_STATE;
+  a.d_in = p->dbuf[p->cur_d];
+  a.d_out = p->dbuf[1 - p->cur_d];
+  a.done = nullptr;
+  STCHK(launch_rows(p, a));
+  p->cur_d = 1 - p->cur_d;
+  return DECONV_OK;
+}
+
+struct IterFlags {
+  int check, store_v, store_x, last;
+};
+
+static IterFlags flags_for(const deconv_plan_s* p, int it, int iters) {
+  const int K = p->opt.check_every;
+  IterFlags f{};
+  f.last = it == iters - 1;
+  f.check = K > 0 && ((it + 1) % K == 0);
+  f.store_v = f.last || (K > 0 && (K == 1 || ((it + 2) % K == 0)));
+  f.store_x = f.last || f.check;
+  return f;
+}
+
+// one iteration: column pass then row pass (+ residual reduction)
+static deconv_status launch_iteration(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
+                                      IterFlags f, float* x_out, float2* u_out, float4* spec_store,
+                                      int iters_since) {
+  ColArgs ca = col_args(p, mu);
+  ca.spec_store = spec_store;
+  STCHK(launch_cols(p, ca));
+  RowArgs ra = row_args(p, mask, lam, mu);
+  ra.mode = ROW_ITER;
+  ra.d_in = p->dbuf[p->cur_d];
+  ra.d_out = p->dbuf[1 - p->cur_d];
+  ra.check = f.check;
+  ra.store_v = f.store_v;
+  ra.store_x = f.store_x;
+  ra.last = f.last;
+  ra.x_out = x_out;
+  ra.u_out = u_out;
+  STCHK(launch_rows(p, ra));
+  p->cur_d = 1 - p->cur_d;
+  if (f.check) {
+    hipLaunchKernelGGL(residual_kernel, dim3(p->batch), dim3(kNT), 0, p->ls, p->d_meta, p->partials, p->res,
+                       p->done, p->nonfinite, p->iters_done, iters_since, p->opt.tol_primal, p->opt.tol_dual);
+    HIPCHK(hipGetLastError());
+  }
+  return DECONV_OK;
+}
+
+static deconv_status copy_ckpt(deconv_plan_s* p, int slot, bool to_store) {
+  const size_t n = (size_t)p->total_px;
+  hipStream_t s = p->stream;
+  float* yt = p->ck_yt + n * slot;
+  float2* v = p->ck_v + n * slot;
+  float2* d = p->ck_d + n * slot;
+  if (to_store) {
+    HIPCHK(hipMemcpyAsync(yt, p->yt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(v, p->v, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(d, p->dbuf[p->cur_d], sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPCHK(hipMemcpyAsync(p->yt, yt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->v, v, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->dbuf[p->cur_d], d, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+  }
+  return DECONV_OK;
+}
+
+// iterate from the current spectra; handles checkpoints, graphs, stopping
+static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
+                             int iters, float* x_out, bool record_ckpt) {
+  hipStream_t s = p->stream;
+  const int K = p->opt.check_every;
+  const int ck = record_ckpt ? p->opt.ckpt_every : 0;
+  const bool stopping = K > 0 && (p->opt.tol_primal > 0 || p->opt.tol_dual > 0);
+  if (ck > 0) {
+    STCHK(copy_ckpt(p, 0, true));
+    p->nck = 1;
+  }
+  int it = 0;
+  while (it < iters) {
+    // graph replay of whole check periods (no checkpoint inside, not the last)
+    if (p->opt.use_graph && K > 0 && ck == 0 && it % K == 0 && it + K < iters) {
+      const int cur0 = p->cur_d;
+      std::vector<uintptr_t> key = {(uintptr_t)K, (uintptr_t)cur0, (uintptr_t)mask, (uintptr_t)lam,
+                                    (uintptr_t)mu, (uintptr_t)x_out};
+      auto g = p->graphs.find(key);
+      if (g == p->graphs.end()) {
+        // capture on the private stream (the caller's may be the null
+        // stream, which cannot be captured); the graph is replayed on the
+        // caller's stream
+        hipGraph_t graph;
+        HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        p->ls = p->cap_stream;
+        deconv_status st = DECONV_OK;
+        for (int q = 0; q < K && st == DECONV_OK; ++q)
+          st = launch_iteration(p, mask, lam, mu, flags_for(p, q, iters + K), x_out, nullptr, nullptr, K);
+        hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+        p->ls = p->stream;
+        p->cur_d = cur0;   // capturing ran nothing
+        if (st != DECONV_OK) return st;
+        if (e != hipSuccess) return DECONV_ERR_HIP;
+        hipGraphExec_t exec;
+        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+        g = p->graphs.emplace(key, exec).first;
+      }
+      HIPCHK(hipGraphLaunch(g->second, s));
+      if (K % 2) p->cur_d = 1 - cur0;
+      it += K;
+      if (stopping) {
+        std::vector<int> dn(p->batch);
+        HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * p->batch, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
+      }
+      continue;
+    }
+    IterFlags f = flags_for(p, it, iters);
+    if (ck > 0 && ((it + 1) % ck == 0) && it + 1 < iters) f.store_v = 1;
+    STCHK(launch_iteration(p, mask, lam, mu, f, x_out, nullptr, nullptr, K));
+    ++it;
+    if (ck > 0 && (it % ck == 0) && it < iters) {
+      STCHK(copy_ckpt(p, it / ck, true));
+      p->nck = it / ck + 1;
+    }
+    if (stopping && f.check) {
+      std::vector<int> dn(p->batch);
+      HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * p->batch, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
+    }
+  }
+  // an early stop skipped the final store of x and v for the images that had
+  // already converged: they stored x at their converging check iteration.
+  return DECONV_OK;
+}
+
+static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deconv_stats* stats) {
+  hipStream_t s = p->stream;
+  if (ytilde_out)
+    HIPCHK(hipMemcpyAsync(ytilde_out, p->yt, sizeof(float) * p->total_px, hipMemcpyDeviceToDevice, s));
+  if (stats) {
+    const int B = p->batch;
+    std::vector<int> dn(B), itd(B), nf(B);
+    std::vector<double> res(3 * B);
+    HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(itd.data(), p->iters_done, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(nf.data(), p->nonfinite, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(res.data(), p->res, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    deconv_status ret = DECONV_OK;
+    for (int b = 0; b < B; ++b) {
+      stats[b].iters_done = dn[b] ? itd[b] : iters;
+      stats[b].r_primal = res[3 * b];
+      stats[b].r_dual = res[3 * b + 1];
+      stats[b].r_z = res[3 * b + 2];
+      stats[b].status = nf[b] ? DECONV_ERR_NONFINITE : DECONV_OK;
+      if (nf[b]) ret = DECONV_ERR_NONFINITE;
+    }
+    return ret;
+  }
+  return DECONV_OK;
+}
+
+static deconv_status reset_counters(deconv_plan_s* p) {
+  hipStream_t s = p->stream;
+  const int B = p->batch;
+  HIPCHK(hipMemsetAsync(p->done, 0, sizeof(int) * B, s));
+  HIPCHK(hipMemsetAsync(p->nonfinite, 0, sizeof(int) * B, s));
+  HIPCHK(hipMemsetAsync(p->iters_done, 0, sizeof(int) * B, s));
+  HIPCHK(hipMemsetAsync(p->res, 0, sizeof(double) * 3 * B, s));
+  return DECONV_OK;
+}
+
+static bool needs_mask(const deconv_plan_s* p) {
+  for (auto& d : p->desc)
+    if (d.mask_kind == DECONV_MASK_EXPLICIT) return true;
+  return false;
+}
+
+extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const uint8_t* mask, const float* h,
+                                         const float* lambda, const float* mu, int32_t iters, float* x_out,
+                                         float* ytilde_out, deconv_stats* stats) {
+  if (!p || !y || !h || !lambda || !mu || !x_out || iters < 1) return DECONV_ERR_INVALID_ARG;
+  if (needs_mask(p) && !mask) return DECONV_ERR_INVALID_ARG;
+  const bool ckpt = p->opt.ckpt_every > 0;
+  if (ckpt && iters > p->opt.max_iters) return DECONV_ERR_INVALID_ARG;
+  hipStream_t s = p->stream;
+  p->have_state = false;
+  p->ck_valid = false;
+  STCHK(setup_spectrum(p, h, nullptr));
+  STCHK(reset_counters(p));
+  hipLaunchKernelGGL(observed_mean_kernel, dim3(p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean);
+  HIPCHK(hipGetLastError());
+  p->cur_d = 0;
+  hipLaunchKernelGGL(init_state_kernel, dim3(64, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean, p->yt,
+                     p->v, p->dbuf[0]);
+  HIPCHK(hipGetLastError());
+  STCHK(prologue_from_state(p, mu));
+  STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
+  p->have_state = true;
+  p->last_iters = iters;
+  p->ck_valid = ckpt;
+  return finish(p, iters, ytilde_out, stats);
+}
+
+extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const float* mu, int32_t iters,
+                                              float* x_out, float* ytilde_out, deconv_stats* stats) {
+  if (!p || !lambda || !mu || !x_out || iters < 1) return DECONV_ERR_INVALID_ARG;
+  if (!p->have_state) return DECONV_ERR_STATE;
+  // the mask pointer is not retained: continuing requires implicit masks
+  if (needs_mask(p)) return DECONV_ERR_INVALID_ARG;
+  p->ck_valid = false;
+  STCHK(reset_counters(p));
+  STCHK(prologue_from_state(p, mu));
+  STCHK(iterate(p, nullptr, lambda, mu, iters, x_out, false));
+  return finish(p, iters, ytilde_out, stats);
+}
+
+extern "C" deconv_status deconv_state_export(deconv_plan p, float* ytilde, float* v, float* d) {
+  if (!p || !ytilde || !v || !d) return DECONV_ERR_INVALID_ARG;
+  if (!p->have_state) return DECONV_ERR_STATE;
+  hipStream_t s = p->stream;
+  const size_t n = (size_t)p->total_px;
+  HIPCHK(hipMemcpyAsync(ytilde, p->yt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(v, p->v, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(d, p->dbuf[p->cur_d], sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_state_import(deconv_plan p, const float* h, const float* mu, const float* ytilde,
+                                             const float* v, const float* d) {
+  if (!p || !h || !mu || !ytilde || !v || !d) return DECONV_ERR_INVALID_ARG;
+  if (needs_mask(p)) return DECONV_ERR_INVALID_ARG;
+  hipStream_t s = p->stream;
+  const size_t n = (size_t)p->total_px;
+  STCHK(setup_spectrum(p, h, nullptr));
+  HIPCHK(hipMemcpyAsync(p->yt, ytilde, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->v, v, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+  p->cur_d = 0;
+  HIPCHK(hipMemcpyAsync(p->dbuf[0], d, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
+  p->have_state = true;
+  p->ck_valid = false;
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_blur_spectrum(deconv_plan p, const float* h, float* spectrum_out) {
+  if (!p || !h || !spectrum_out) return DECONV_ERR_INVALID_ARG;
+  deconv_status st = setup_spectrum(p, h, spectrum_out);
+  if (st != DECONV_OK) return st;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* data, int32_t inverse,
+                                     void* stream) {
+  if (count < 1 || !data) return DECONV_ERR_INVALID_ARG;
+  if (!supported_len(height) || !supported_len(width)) return DECONV_ERR_UNSUPPORTED_SIZE;
+  if ((int)fftrow_lds_bytes(width) > max_lds_bytes() || (int)fftcol_lds_bytes(height) > max_lds_bytes())
+    return DECONV_ERR_UNSUPPORTED_SIZE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float2* twr = cached_twiddles(width);
+  const float2* twc = cached_twiddles(height);
+  if (!twr || !twc) return DECONV_ERR_HIP;
+  float2* g = reinterpret_cast<float2*>(data);
+  HIPCHK(launch_fft_rows(width, g, (long long)count * height, twr, inverse ? 1 : 0, s));
+  HIPCHK(launch_fft_cols(height, g, width, count, twc, inverse ? 1 : 0, s));
+  return DECONV_OK;
+}
+
+#include "backward_host.inc"
+
+extern "C" const char* deconv_status_str(deconv_status s) {
+  switch (s) {
+    case DECONV_OK: return "ok";
+    case DECONV_ERR_INVALID_ARG: return "invalid argument";
+    case DECONV_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+    case DECONV_ERR_SINGULAR: return "blur has zero DC gain (sum(h) == 0)";
+    case DECONV_ERR_NONFINITE: return "non-finite values in the iteration";
+    case DECONV_ERR_NO_CHECKPOINTS: return "backward needs a checkpointed forward run";
+    case DECONV_ERR_HIP: return "HIP runtime error";
+    case DECONV_ERR_OOM: return "out of memory / workspace too small";
+    case DECONV_ERR_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}

@@ -1,0 +1,534 @@
+// HIP kernels of the partial ADMM (arXiv 1602.01410, Sec. II-B and III-B).
+//
+// One iteration i -> i+1 of eqs. (admm_aprox_1)-(admm_aprox_4) is two launches:
+//
+//   column pass  (one workgroup per block of C half-spectrum columns)
+//     forward column DFT of the row spectra of ytilde^i and mu*D^T(v^i-d^i),
+//     spectral solve of the x-step (dual_x_iter_resolved_boundaries):
+//        X = (conj(H) Y + mu G) / (|H|^2 + mu(|D_h|^2 + |D_v|^2)),
+//     Q = H X, inverse column DFT of X and Q.
+//   row pass     (one workgroup per tile of RT image rows)
+//     inverse row DFT of X + iQ on RT+2 rows (one halo row above and below)
+//     -> x^{i+1} (real part) and H x^{i+1} (imaginary part);
+//     z-step with relaxation alpha on the unobserved pixels;
+//     u = D x^{i+1} + d^i, vector soft threshold -> v^{i+1}, d^{i+1} = u - v;
+//     right-hand side of the next x-step: g = D^T(v^{i+1} - d^{i+1}),
+//     forward row DFT of ytilde^{i+1} + i mu g, split into the two real
+//     signals' half spectra (Hermitian symmetry), stored for the next
+//     column pass.
+//
+// Only the state (ytilde, d, and v on the iterations that need it) and the
+// two half-spectrum buffers touch HBM; x and H x never leave LDS.
+//
+// Half-spectrum buffer layout ("tiled"): for an image with m' rows, nh = n'/2+1
+// spectrum columns grouped in nb blocks of C columns, element (row i, column
+// kx) of the pair of signals is the float4 at ((kx / C) * m' + i) * C + kx % C.
+// A column pass reads one block as a contiguous run; a row pass reads C
+// columns x (RT+2) rows contiguously per block.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+
+namespace dcv {
+
+constexpr int kNT = 256;   // threads per workgroup of every ADMM kernel
+
+// rows per row-pass tile and columns per column-pass block, by line length
+__host__ __device__ constexpr int rt_for(int L) {
+  return 4096 / L < 2 ? 2 : (4096 / L > 32 ? 32 : 4096 / L);
+}
+__host__ __device__ constexpr int c_for(int L) {
+  int c = 1;
+  while (c * 2 <= 2048 / L && c * 2 <= 16) c *= 2;
+  return c;
+}
+__host__ __device__ constexpr int row_lds_elems(int L) { return (rt_for(L) + 2) * lstride(L) + L; }
+__host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + L; }
+
+struct ImgMeta {
+  int m, n;            // m' (rows), n' (columns)
+  int b;               // kernel half size
+  int mask_kind, decim;
+  int nh, C, logC, nb; // half-spectrum columns, block width (power of 2), blocks
+  int rt;              // rows per row tile
+  int nrt;             // row tiles
+  int pad_;
+  long long px;        // offset of the image in pixel arrays
+  long long sp;        // offset in half-spectrum buffers (float4 units)
+  long long hh;        // offset in the blur half spectrum (float2 units)
+  long long tab;       // offset in the |D|^2 tables (float)
+  long long twr, twc;  // twiddle table offsets for lengths n' and m'
+  long long rt0;       // first row-tile index of the image (residual partials)
+};
+
+enum { ROW_ITER = 0, ROW_STATE = 1 };
+
+struct RowArgs {
+  const ImgMeta* meta;
+  const int4* tiles;         // (image, first row, -, -)
+  const float4* spec_in;     // column-pass output (X, Q) half spectra
+  float4* spec_out;          // (Y, mu G) half spectra for the next column pass
+  float* yt;                 // ytilde = [y; z] on the extended grid
+  const float2* d_in;        // d^i (double-buffered: halo rows are read by neighbours)
+  float2* d_out;             // d^{i+1}
+  float2* v;                 // v (read on check iterations, written when store_v)
+  float* x_out;              // x^{i+1} (when store_x)
+  float2* u_out;             // u = D x + d (backward recompute), nullable
+  const uint8_t* mask;       // explicit masks
+  const float* lam;
+  const float* mu;
+  const float2* tw;          // twiddle tables
+  double* partials;          // 3 doubles per row tile (when check)
+  const int* done;           // per-image stop flags, nullable
+  float alpha;
+  int mode, check, store_v, store_x, last;
+};
+
+struct ColArgs {
+  const ImgMeta* meta;
+  const int4* tiles;         // (image, block, -, -)
+  const float4* spec_in;
+  float4* spec_out;
+  const float2* hh;          // blur half spectrum, tiled like the spectra (float2)
+  const float* tab;          // per image: |D_v|^2[m'] then |D_h|^2[nb*C]
+  const float* mu;
+  const float2* tw;
+  float4* spec_store;        // (Y, X) per frequency for the backward, nullable
+  const int* done;
+};
+
+__device__ __forceinline__ bool observed(const ImgMeta& mt, const uint8_t* __restrict__ mask,
+                                         int i, int j) {
+  if (mt.mask_kind == 1) return mask[mt.px + (long long)i * mt.n + j] != 0;
+  const bool in_c = i >= mt.b && i < mt.m - mt.b && j >= mt.b && j < mt.n - mt.b;
+  if (mt.mask_kind == 2) return in_c && ((i - mt.b) % mt.decim) == 0 && ((j - mt.b) % mt.decim) == 0;
+  return in_c;
+}
+
+__device__ __forceinline__ int wrapi(int i, int M) { return i < 0 ? i + M : (i >= M ? i - M : i); }
+
+// sum three doubles over the workgroup; result valid in thread 0
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* scratch) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+    c += __shfl_xor(c, off);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) { scratch[3 * wv] = a; scratch[3 * wv + 1] = b; scratch[3 * wv + 2] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = b = c = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += scratch[3 * w]; b += scratch[3 * w + 1]; c += scratch[3 * w + 2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row pass
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
+  constexpr int RT = rt_for(L);
+  constexpr int LS = lstride(L);
+  constexpr int KP = ((RT + 1) * L + kNT - 1) / kNT;  // pixels per thread (own rows + 1 halo)
+  const ImgMeta mt = a.meta[img];
+  const int M = mt.m;
+  const int nr = min(RT, M - r0);
+  const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
+  float2* buf = lds;
+  float2* tw = lds + (RT + 2) * LS;
+  load_twiddles<L, kNT>(tw, a.tw + mt.twr);
+  const float mu = a.mu[img];
+  const float tau = a.lam[img] / mu;
+  const int npx = (nr + 1) * L;   // rows r0-1 .. r0+nr-1
+  float ynew[KP];
+  float2 wreg[KP];
+  float rd = 0.f, rv = 0.f, rz = 0.f;
+
+  if (a.mode == ROW_ITER) {
+    // gather X + iQ for rows r0-1 .. r0+nr (Hermitian completion of the half spectra)
+    const float4* __restrict__ sin = a.spec_in + mt.sp;
+    const int nl = nr + 2;
+    const int tot = nb * nl * C;
+    for (int q = threadIdx.x; q < tot; q += kNT) {
+      const int c = q & (C - 1);
+      const int t2 = q >> logC;
+      const int l = t2 % nl, blk = t2 / nl;
+      const int kx = blk * C + c;
+      if (kx >= nh) continue;
+      const int i = wrapi(r0 - 1 + l, M);
+      const float4 v = sin[((long long)blk * M + i) * C + c];
+      float2* line = buf + l * LS;
+      line[lpad(kx)] = make_float2(v.x - v.w, v.y + v.z);
+      if (kx >= 1 && kx <= L - nh) line[lpad(L - kx)] = make_float2(v.x + v.w, v.z - v.y);
+    }
+    __syncthreads();
+    fft_lines<L, true, kNT, RT + 2>(buf, nl, tw);
+
+    // epilogue: z-step, TV prox, dual update for rows r0-1 .. r0+nr-1
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = threadIdx.x + k * kNT;
+      if (p < npx) {
+        const int l = p / L, j = p - l * L;
+        const int i = wrapi(r0 - 1 + l, M);
+        const float2 c0 = buf[l * LS + lpad(j)];
+        const float x = c0.x;
+        const float xr = buf[l * LS + lpad(j + 1 == L ? 0 : j + 1)].x;
+        const float xd = buf[(l + 1) * LS + lpad(j)].x;
+        const long long pix = mt.px + (long long)i * L + j;
+        const float2 dd = a.d_in[pix];
+        const float uh = xr - x + dd.x, uv = xd - x + dd.y;
+        const float nrm = sqrtf(uh * uh + uv * uv);
+        const float s = nrm > tau ? (nrm - tau) / nrm : 0.f;
+        const float vh = s * uh, vv = s * uv;
+        const float dh = uh - vh, dv = uv - vv;
+        wreg[k] = make_float2(vh - dh, vv - dv);
+        if (l >= 1) {
+          a.d_out[pix] = make_float2(dh, dv);
+          rd += (dh - dd.x) * (dh - dd.x) + (dv - dd.y) * (dv - dd.y);
+          if (a.check) {
+            const float2 vo = a.v[pix];
+            rv += (vh - vo.x) * (vh - vo.x) + (vv - vo.y) * (vv - vo.y);
+          }
+          if (a.store_v) a.v[pix] = make_float2(vh, vv);
+          const float yo = a.yt[pix];
+          float yn = yo;
+          if (!observed(mt, a.mask, i, j)) {
+            yn = yo + a.alpha * (c0.y - yo);
+            a.yt[pix] = yn;
+            rz += (yn - yo) * (yn - yo);
+          }
+          ynew[k] = yn;
+          if (a.store_x) a.x_out[pix] = x;
+          if (a.u_out) a.u_out[pix] = make_float2(uh, uv);
+        }
+      }
+    }
+  } else {
+    // ROW_STATE: start from a stored state (v, d, ytilde)
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = threadIdx.x + k * kNT;
+      if (p < npx) {
+        const int l = p / L, j = p - l * L;
+        const int i = wrapi(r0 - 1 + l, M);
+        const long long pix = mt.px + (long long)i * L + j;
+        const float2 vv = a.v[pix], dd = a.d_in[pix];
+        wreg[k] = make_float2(vv.x - dd.x, vv.y - dd.y);
+        if (l >= 1) {
+          ynew[k] = a.yt[pix];
+          a.d_out[pix] = dd;
+        }
+      }
+    }
+  }
+
+  if (a.check) {
+    __shared__ double red[3 * (kNT / 64)];
+    double rdd = rd, rvd = rv, rzd = rz;
+    block_sum3(rdd, rvd, rzd, red);
+    if (threadIdx.x == 0) {
+      double* out = a.partials + 3 * (mt.rt0 + r0 / RT);
+      out[0] = rdd; out[1] = rvd; out[2] = rzd;
+    }
+  }
+  if (a.last) return;
+
+  // prologue of the next x-step: g = D^T w with w = v - d, pack ytilde + i mu g
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      buf[l * LS + lpad(j)] = wreg[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      if (l >= 1) {
+        const float2 w = buf[l * LS + lpad(j)];
+        const float whl = buf[l * LS + lpad(j == 0 ? L - 1 : j - 1)].x;
+        const float wvu = buf[(l - 1) * LS + lpad(j)].y;
+        wreg[k] = make_float2(ynew[k], mu * (whl - w.x + wvu - w.y));
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = threadIdx.x + k * kNT;
+    if (p < npx) {
+      const int l = p / L, j = p - l * L;
+      if (l >= 1) buf[l * LS + lpad(j)] = wreg[k];
+    }
+  }
+  __syncthreads();
+  fft_lines<L, false, kNT, RT>(buf + LS, nr, tw);
+
+  // split C = F(ytilde) + i F(mu g) into the two half spectra and store
+  float4* __restrict__ sout = a.spec_out + mt.sp;
+  const int tot2 = nb * nr * C;
+  for (int q = threadIdx.x; q < tot2; q += kNT) {
+    const int c = q & (C - 1);
+    const int t2 = q >> logC;
+    const int l = t2 % nr, blk = t2 / nr;
+    const int kx = blk * C + c;
+    if (kx >= nh) continue;
+    const float2 cf = buf[(l + 1) * LS + lpad(kx)];
+    const float2 cm = buf[(l + 1) * LS + lpad(kx == 0 ? 0 : L - kx)];
+    sout[((long long)blk * M + r0 + l) * C + c] =
+        make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kNT) row_kernel(RowArgs a) {
+  extern __shared__ float2 lds[];
+  const int4 t = a.tiles[blockIdx.x];
+  if (a.done && a.done[t.x]) return;
+  row_tile<L>(a, t.x, t.y, lds);
+}
+
+// ---------------------------------------------------------------------------
+// column pass
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, float2* lds) {
+  constexpr int C = c_for(L);
+  constexpr int LS = lstride(L);
+  const ImgMeta mt = a.meta[img];
+  float2* buf = lds;
+  float2* tw = lds + 2 * C * LS;
+  load_twiddles<L, kNT>(tw, a.tw + mt.twc);
+  const long long base = mt.sp + (long long)blk * L * C;
+  const float4* __restrict__ sin = a.spec_in + base;
+  for (int q = threadIdx.x; q < L * C; q += kNT) {
+    const int i = q / C, c = q - i * C;
+    const float4 v = sin[q];
+    buf[(2 * c) * LS + lpad(i)] = make_float2(v.x, v.y);
+    buf[(2 * c + 1) * LS + lpad(i)] = make_float2(v.z, v.w);
+  }
+  __syncthreads();
+  fft_lines<L, false, kNT, 2 * C>(buf, 2 * C, tw);
+
+  const float mu = a.mu[img];
+  const float scale = 1.0f / ((float)L * (float)mt.n);
+  const float2* __restrict__ hh = a.hh + mt.hh + (long long)blk * L * C;
+  const float* __restrict__ dv2 = a.tab + mt.tab;
+  const float* __restrict__ dh2 = dv2 + L;
+  for (int q = threadIdx.x; q < L * C; q += kNT) {
+    const int ky = q / C, c = q - ky * C;
+    const int kx = blk * C + c;
+    const float2 Y = buf[(2 * c) * LS + lpad(ky)];
+    const float2 G = buf[(2 * c + 1) * LS + lpad(ky)];
+    float2 X = make_float2(0.f, 0.f), Q = X;
+    if (kx < mt.nh) {
+      const float2 Hk = hh[q];
+      const float den = Hk.x * Hk.x + Hk.y * Hk.y + mu * (dh2[kx] + dv2[ky]);
+      const float inv = scale / den;
+      // conj(H) Y + G
+      X = make_float2((Hk.x * Y.x + Hk.y * Y.y + G.x) * inv, (Hk.x * Y.y - Hk.y * Y.x + G.y) * inv);
+      Q = cmul(Hk, X);
+      if (a.spec_store) a.spec_store[base + q] = make_float4(Y.x, Y.y, X.x, X.y);
+    }
+    buf[(2 * c) * LS + lpad(ky)] = X;
+    buf[(2 * c + 1) * LS + lpad(ky)] = Q;
+  }
+  __syncthreads();
+  fft_lines<L, true, kNT, 2 * C>(buf, 2 * C, tw);
+  float4* __restrict__ sout = a.spec_out + base;
+  for (int q = threadIdx.x; q < L * C; q += kNT) {
+    const int i = q / C, c = q - i * C;
+    const float2 X = buf[(2 * c) * LS + lpad(i)];
+    const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
+    sout[q] = make_float4(X.x, X.y, Q.x, Q.y);
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kNT) col_kernel(ColArgs a) {
+  extern __shared__ float2 lds[];
+  const int4 t = a.tiles[blockIdx.x];
+  if (a.done && a.done[t.x]) return;
+  col_tile<L>(a, t.x, t.y, lds);
+}
+
+// ---------------------------------------------------------------------------
+// plain batched 2-D FFT passes (setup of the blur spectrum, diagnostics)
+// data: float2 [count][H][W] row-major
+// ---------------------------------------------------------------------------
+template <int L>  // L = W
+__global__ void __launch_bounds__(kNT) fft_rows_kernel(float2* data, long long nrows_total,
+                                                       const float2* tw_glob, int inverse) {
+  extern __shared__ float2 lds[];
+  constexpr int LPW = 4096 / L < 1 ? 1 : (4096 / L > 32 ? 32 : 4096 / L);
+  constexpr int LS = lstride(L);
+  float2* tw = lds + LPW * LS;
+  load_twiddles<L, kNT>(tw, tw_glob);
+  const long long row0 = (long long)blockIdx.x * LPW;
+  const int nl = (int)min((long long)LPW, nrows_total - row0);
+  for (int q = threadIdx.x; q < nl * L; q += kNT) {
+    const int l = q / L, j = q - l * L;
+    lds[l * LS + lpad(j)] = data[(row0 + l) * L + j];
+  }
+  __syncthreads();
+  if (inverse) fft_lines<L, true, kNT, LPW>(lds, nl, tw);
+  else fft_lines<L, false, kNT, LPW>(lds, nl, tw);
+  for (int q = threadIdx.x; q < nl * L; q += kNT) {
+    const int l = q / L, j = q - l * L;
+    data[(row0 + l) * L + j] = lds[l * LS + lpad(j)];
+  }
+}
+
+template <int L>  // L = H
+__global__ void __launch_bounds__(kNT) fft_cols_kernel(float2* data, int W, int count,
+                                                       const float2* tw_glob, int inverse) {
+  extern __shared__ float2 lds[];
+  constexpr int CW = c_for(L) * 2;   // columns per workgroup
+  constexpr int LS = lstride(L);
+  float2* tw = lds + CW * LS;
+  load_twiddles<L, kNT>(tw, tw_glob);
+  const int nblk = (W + CW - 1) / CW;
+  const int img = blockIdx.x / nblk, blk = blockIdx.x - img * nblk;
+  if (img >= count) return;
+  float2* base = data + (long long)img * L * W;
+  const int c0 = blk * CW;
+  const int nc = min(CW, W - c0);
+  for (int q = threadIdx.x; q < L * CW; q += kNT) {
+    const int i = q / CW, c = q - i * CW;
+    if (c < nc) lds[c * LS + lpad(i)] = base[(long long)i * W + c0 + c];
+  }
+  __syncthreads();
+  if (inverse) fft_lines<L, true, kNT, CW>(lds, nc, tw);
+  else fft_lines<L, false, kNT, CW>(lds, nc, tw);
+  for (int q = threadIdx.x; q < L * CW; q += kNT) {
+    const int i = q / CW, c = q - i * CW;
+    if (c < nc) base[(long long)i * W + c0 + c] = lds[c * LS + lpad(i)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup and initialisation
+// ---------------------------------------------------------------------------
+
+// embed kernel b circularly centred at the origin into a complex m' x n' grid
+__global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ h,
+                                 const long long* hoff, float2* grid, const long long* goff) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const long long n = (long long)mt.m * mt.n;
+  float2* g = grid + goff[img];
+  const int K = 2 * mt.b + 1;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
+    // position (i, j) collects h[b+p][b+q] with p = i (mod m'), q = j (mod n')
+    float s = 0.f;
+    for (int pp = -mt.b; pp <= mt.b; ++pp) {
+      if (((pp % mt.m) + mt.m) % mt.m != i) continue;
+      for (int qq = -mt.b; qq <= mt.b; ++qq)
+        if (((qq % mt.n) + mt.n) % mt.n == j) s += h[hoff[img] + (long long)(mt.b + pp) * K + (mt.b + qq)];
+    }
+    g[p] = make_float2(s, 0.f);
+  }
+}
+
+// copy the spectrum columns kx < nh into the tiled half layout
+__global__ void pack_half_kernel(const ImgMeta* meta, const float2* __restrict__ grid,
+                                 const long long* goff, float2* hh) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const long long tot = (long long)mt.m * mt.nb * mt.C;
+  const float2* g = grid + goff[img];
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < tot;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(q % mt.C);
+    const long long t = q / mt.C;
+    const int ky = (int)(t % mt.m), blk = (int)(t / mt.m);
+    const int kx = blk * mt.C + c;
+    hh[mt.hh + q] = kx < mt.nh ? g[(long long)ky * mt.n + kx] : make_float2(0.f, 0.f);
+  }
+}
+
+// per image: mean of the observed pixels (FP64)
+__global__ void __launch_bounds__(kNT) observed_mean_kernel(const ImgMeta* meta, const float* __restrict__ y,
+                                                           const uint8_t* __restrict__ mask, double* mean) {
+  const int img = blockIdx.x;
+  const ImgMeta mt = meta[img];
+  double s = 0.0, c = 0.0, dummy = 0.0;
+  const long long n = (long long)mt.m * mt.n;
+  for (long long p = threadIdx.x; p < n; p += kNT) {
+    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
+    if (observed(mt, mask, i, j)) { s += y[mt.px + p]; c += 1.0; }
+  }
+  __shared__ double red[3 * (kNT / 64)];
+  block_sum3(s, c, dummy, red);
+  if (threadIdx.x == 0) mean[img] = c > 0 ? s / c : 0.0;
+}
+
+__device__ __forceinline__ float init_value(const ImgMeta& mt, const float* __restrict__ y,
+                                            const uint8_t* __restrict__ mask, float mean, int i, int j) {
+  if (observed(mt, mask, i, j)) return y[mt.px + (long long)i * mt.n + j];
+  const bool in_c = i >= mt.b && i < mt.m - mt.b && j >= mt.b && j < mt.n - mt.b;
+  if (in_c) return mean;
+  const int si = min(max(i, mt.b), mt.m - mt.b - 1), sj = min(max(j, mt.b), mt.n - mt.b - 1);
+  return observed(mt, mask, si, sj) ? y[mt.px + (long long)si * mt.n + sj] : mean;
+}
+
+// ytilde^0, v^0 = D ytilde^0, d^0 = 0
+__global__ void init_state_kernel(const ImgMeta* meta, const float* __restrict__ y,
+                                  const uint8_t* __restrict__ mask, const double* mean, float* yt,
+                                  float2* v, float2* d) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const long long n = (long long)mt.m * mt.n;
+  const float mn = (float)mean[img];
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
+    const float c = init_value(mt, y, mask, mn, i, j);
+    const float r = init_value(mt, y, mask, mn, i, j + 1 == mt.n ? 0 : j + 1);
+    const float dn = init_value(mt, y, mask, mn, i + 1 == mt.m ? 0 : i + 1, j);
+    yt[mt.px + p] = c;
+    v[mt.px + p] = make_float2(r - c, dn - c);
+    d[mt.px + p] = make_float2(0.f, 0.f);
+  }
+}
+
+// per image: FP64 sum of the row-tile partials -> |d'-d|, |v'-v|, |z'-z|;
+// optionally sets the stop flag
+__global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, const double* partials,
+                                                       double* res, int* done, int* nonfinite,
+                                                       int* iters_done, int iters_since,
+                                                       double tol_p, double tol_d) {
+  const int img = blockIdx.x;
+  const ImgMeta mt = meta[img];
+  double a = 0, b = 0, c = 0;
+  for (int t = threadIdx.x; t < mt.nrt; t += kNT) {
+    const double* p = partials + 3 * (mt.rt0 + t);
+    a += p[0]; b += p[1]; c += p[2];
+  }
+  __shared__ double red[3 * (kNT / 64)];
+  block_sum3(a, b, c, red);
+  if (threadIdx.x == 0) {
+    if (done && done[img]) return;
+    res[3 * img] = sqrt(a); res[3 * img + 1] = sqrt(b); res[3 * img + 2] = sqrt(c);
+    if (!isfinite(a) || !isfinite(b) || !isfinite(c)) nonfinite[img] = 1;
+    iters_done[img] += iters_since;
+    const double sc = sqrt(2.0 * (double)mt.m * (double)mt.n);
+    if (done && (tol_p > 0 || tol_d > 0) && sqrt(a) <= tol_p * sc && sqrt(b) <= tol_d * sc) done[img] = 1;
+  }
+}
+
+}  // namespace dcv

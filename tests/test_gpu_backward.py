@@ -1,0 +1,71 @@
+"""Adjoint kernels vs the FP64 hand-written oracle adjoint (which is itself
+pinned by central finite differences in the CPU tests)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_01410_amd import synth
+
+from .gpu_util import desc, device_inputs, explicit_mask, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems():
+    return [synth.problem(24, 18, 5, "rect", "random", mask_kind=synth.MASK_EXPLICIT, missing=0.2, bsnr=40.0,
+                          lam=3e-3, mu=0.05, seed=71, nrect=5),
+            synth.problem(48, 64, 7, "rect", "random", mask_kind=synth.MASK_DECIMATE, decim=2, bsnr=40.0,
+                          lam=5e-3, mu=0.08, seed=72, nrect=5),
+            synth.problem(72, 72, 9, "rect", "gauss", sigma=2.0, bsnr=45.0, lam=1e-3, mu=0.05, seed=73)]
+
+
+@pytest.mark.parametrize("iters,ck", [(6, 2), (7, 3), (5, 5)])
+def test_backward_matches_oracle(iters, ck):
+    import torch
+    from paper_1602_01410_amd import binding
+    probs = _problems()
+    plan = binding.Plan([desc(p) for p in probs], ckpt_every=ck, max_iters=iters)
+    y, mask, h, lam, mu = device_inputs(probs)
+    x, _ = plan.run(y, mask, h, lam, mu, iters)
+    rng = np.random.default_rng(iters * 10 + ck)
+    gxs = [rng.standard_normal((p["M"], p["N"])).astype(np.float32) for p in probs]
+    gx = torch.from_numpy(np.concatenate([g.ravel() for g in gxs])).cuda()
+    gy, gl, gh = plan.backward(y, mask, h, lam, mu, gx)
+    torch.cuda.synchronize()
+    gys = [a.cpu().numpy().astype(np.float64) for a in plan.split(gy)]
+    ghs, o = [], 0
+    for p in probs:
+        k = p["K"] * p["K"]
+        ghs.append(gh[o:o + k].cpu().numpy().reshape(p["K"], p["K"]).astype(np.float64))
+        o += k
+    gls = gl.cpu().numpy()
+    for b, p in enumerate(probs):
+        ry, rl, rh = oracle.admm_backward(p["y"].astype(np.float64), explicit_mask(p), p["h"].astype(np.float64),
+                                          float(np.float32(p["lam"])), float(np.float32(p["mu"])), iters,
+                                          gxs[b].astype(np.float64))
+        ey, eh = rel_l2(gys[b], ry), rel_l2(ghs[b], rh)
+        el = abs(float(gls[b]) - rl) / max(abs(rl), 1e-12)
+        log("img%d grad_y %.2e grad_h %.2e grad_lambda %.2e (ref %.4e)" % (b, ey, eh, el, rl))
+        assert ey <= 1e-3 and eh <= 1e-3, (b, ey, eh)
+        assert el <= 1e-3 or abs(float(gls[b]) - rl) <= 1e-6 * np.abs(ry).max(), (b, el)
+
+
+def test_autograd_function():
+    import torch
+    from paper_1602_01410_amd import binding
+    p = _problems()[2]
+    plan = binding.Plan([desc(p)], ckpt_every=4, max_iters=8)
+    y, mask, h, lam, mu = device_inputs([p])
+    y.requires_grad_(True)
+    h.requires_grad_(True)
+    lam.requires_grad_(True)
+    x = binding.admm(y, h, lam, plan, mask, mu, 8)
+    target = torch.from_numpy(p["x_true"].reshape(-1)).cuda()
+    loss = 0.5 * ((x - target) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    ry, rl, rh = oracle.admm_backward(p["y"].astype(np.float64), explicit_mask(p), p["h"].astype(np.float64),
+                                      float(np.float32(p["lam"])), float(np.float32(p["mu"])), 8,
+                                      (x.detach().cpu().numpy() - p["x_true"].reshape(-1)).reshape(p["M"], p["N"]))
+    assert rel_l2(y.grad.cpu().numpy().reshape(p["M"], p["N"]), ry) <= 1e-3
+    assert rel_l2(h.grad.cpu().numpy().reshape(p["K"], p["K"]), rh) <= 1e-3

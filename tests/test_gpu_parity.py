@@ -1,0 +1,200 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_01410_amd import synth
+
+from .gpu_util import (assert_parity, desc, device_inputs, gpu_run, log, oracle_run, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+# --------------------------------------------------------------------------
+# a0: the transforms themselves
+# --------------------------------------------------------------------------
+
+FFT_SHAPES = [(8, 8), (12, 16), (18, 24), (36, 72), (72, 72), (96, 128), (144, 192), (256, 256),
+              (288, 384), (512, 576), (768, 1024), (1152, 1536), (1024, 1024), (2048, 2048)]
+
+
+@pytest.mark.parametrize("shape", FFT_SHAPES)
+def test_fft2_parity(torch_cuda, shape):
+    torch = torch_cuda
+    from paper_1602_01410_amd import binding
+    M, N = shape
+    count = 2 if M * N <= 1 << 20 else 1
+    log("fft2 %dx%d x%d" % (M, N, count))
+    rng = np.random.default_rng(M * 7 + N)
+    x = (rng.standard_normal((count, M, N)) + 1j * rng.standard_normal((count, M, N))).astype(np.complex64)
+    for inverse in (False, True):
+        t = torch.from_numpy(x.copy()).cuda()
+        binding.fft2(t, inverse=inverse)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy()
+        for c in range(count):
+            ref = oracle.fft2(x[c].astype(np.complex128), +1 if inverse else -1)
+            r = rel_l2(got[c], ref)
+            assert r <= 1e-5, (shape, inverse, r)
+
+
+def test_blur_spectrum_and_kappa(torch_cuda):
+    """H^ of the embedded kernel (setup step) vs the oracle; kappa of the
+    paper's tables for the blurs FP32 can resolve."""
+    torch = torch_cuda
+    from paper_1602_01410_amd import binding
+    kernels = [synth.box_kernel(5), synth.box_kernel(13), synth.gaussian_kernel(5, np.sqrt(5)),
+               synth.gaussian_kernel(13, np.sqrt(13)), synth.box_kernel(21), synth.gaussian_kernel(21, np.sqrt(21))]
+    plan = binding.Plan([dict(height=256, width=256, ksize=k.shape[0]) for k in kernels])
+    h = torch.from_numpy(np.concatenate([k.astype(np.float32).ravel() for k in kernels])).cuda()
+    spec = plan.blur_spectrum(h).cpu().numpy().view(np.complex64).reshape(len(kernels), 256, 256)
+    for k, s in zip(kernels, spec):
+        ref = oracle.psf_spectrum(256, 256, k.astype(np.float32).astype(np.float64))
+        assert rel_l2(s, ref) <= 1e-6
+        # kappa: both sides' min |H| must be well above FP32 rounding of max |H|
+        kap_ref = np.abs(ref).max() / np.abs(ref).min()
+        if kap_ref < 1e5:
+            kap = np.abs(s).max() / np.abs(s).min()
+            assert abs(kap - kap_ref) <= 1e-2 * kap_ref, (kap, kap_ref)
+
+
+# --------------------------------------------------------------------------
+# a1..a7: iterations
+# --------------------------------------------------------------------------
+
+def _small(M, N, K, kind=synth.MASK_BOUNDARY, seed=0, decim=3, missing=0.3, blur="random", lam=1e-2, mu=0.05):
+    return synth.problem(M, N, K, "rect", blur, mask_kind=kind, decim=decim, missing=missing, bsnr=40.0,
+                         lam=lam, mu=mu, seed=seed, nrect=6)
+
+
+def test_one_iteration_full_state(torch_cuda):
+    """x^1, ytilde^1, v^1, d^1 after one iteration, per image of a mixed batch."""
+    probs = [_small(24, 32, 5, synth.MASK_EXPLICIT, seed=1), _small(48, 36, 7, synth.MASK_DECIMATE, seed=2),
+             _small(72, 72, 9, synth.MASK_BOUNDARY, seed=3, blur="box")]
+    g = gpu_run(probs, 1, want_state=True)
+    for b, p in enumerate(probs):
+        r = oracle_run(p, 1)
+        log("image %d %dx%d" % (b, p["M"], p["N"]))
+        assert rel_l2(g["x"][b], r["x"]) <= 1e-5
+        assert rel_l2(g["yt"][b], r["yt"]) <= 1e-5
+        vref = np.stack([r["vh"], r["vv"]], -1)
+        dref = np.stack([r["dh"], r["dv"]], -1)
+        # v, d: the soft threshold is 1-Lipschitz, so errors stay at the
+        # level of u = D x + d; v may be all zero after one iteration
+        scale = np.linalg.norm(vref) + np.linalg.norm(dref)
+        assert np.linalg.norm(g["v"][b] - vref) <= 1e-5 * scale
+        assert np.linalg.norm(g["d"][b] - dref) <= 1e-5 * scale
+
+
+def test_plain_72_config_200_iterations(torch_cuda):
+    """72x72 domain, 9x9 box, observed 64x64, BSNR 50, lambda 1e-3, mu 0.05,
+    200 iterations: relative L2 <= 1e-4, max abs <= 1e-3 of the range."""
+    p = synth.config_plain_72()
+    g = gpu_run([p], p["iters"])
+    r = oracle_run(p, p["iters"])
+    assert_parity(g["x"][0], r["x"], what="x")
+    assert_parity(g["yt"][0], r["yt"], what="ytilde")
+
+
+MIXED = [
+    dict(M=48, N=96, K=7, kind=synth.MASK_BOUNDARY),
+    dict(M=96, N=72, K=5, kind=synth.MASK_DECIMATE),
+    dict(M=64, N=64, K=9, kind=synth.MASK_EXPLICIT),
+    dict(M=128, N=192, K=11, kind=synth.MASK_BOUNDARY),
+    dict(M=36, N=18, K=3, kind=synth.MASK_EXPLICIT),
+    dict(M=144, N=128, K=15, kind=synth.MASK_DECIMATE),
+    dict(M=16, N=8, K=3, kind=synth.MASK_BOUNDARY),
+]
+
+
+def _mixed(seed0=10, blur="random"):
+    return [_small(d["M"], d["N"], d["K"], d["kind"], seed=seed0 + i, blur=blur, lam=3e-3, mu=0.05)
+            for i, d in enumerate(MIXED)]
+
+
+@pytest.mark.parametrize("alpha", [2.0, 1.0])
+def test_mixed_batch_parity(torch_cuda, alpha):
+    """Uneven sizes, all mask kinds, asymmetric kernels, one batched plan."""
+    probs = _mixed()
+    iters = 60
+    g = gpu_run(probs, iters, alpha=alpha)
+    for b, p in enumerate(probs):
+        r = oracle_run(p, iters, alpha=alpha)
+        assert_parity(g["x"][b], r["x"], what="img%d %dx%d x" % (b, p["M"], p["N"]))
+        assert_parity(g["yt"][b], r["yt"], what="img%d ytilde" % b)
+
+
+def test_batched_plain_graph_agree(torch_cuda):
+    """Same kernels whatever the launch schedule: batched, per image, graph
+    replay -- bitwise identical outputs."""
+    probs = _mixed(seed0=30)
+    a = gpu_run(probs, 25, batched=1, use_graph=0, check_every=5)
+    b = gpu_run(probs, 25, batched=0, use_graph=0, check_every=5)
+    c = gpu_run(probs, 25, batched=1, use_graph=1, check_every=5)
+    c2 = gpu_run(probs, 26, batched=1, use_graph=1, check_every=5)
+    for i in range(len(probs)):
+        assert np.array_equal(a["x"][i], b["x"][i])
+        assert np.array_equal(a["x"][i], c["x"][i])
+        assert np.array_equal(a["yt"][i], c["yt"][i])
+    # 26 iterations through graph replays + direct launches vs the oracle
+    r = oracle_run(probs[3], 26)
+    assert_parity(c2["x"][3], r["x"], what="graph 26 it")
+
+
+def test_residuals_match_oracle(torch_cuda):
+    probs = _mixed(seed0=40)[:4]
+    iters = 20
+    g = gpu_run(probs, iters, check_every=1, use_graph=0)
+    for b, p in enumerate(probs):
+        r = oracle_run(p, iters)
+        h = r["hist"][-1]
+        st = g["stats"][b]
+        assert st["iters_done"] == iters and st["status"] == 0
+        for key, ref in (("r_primal", h[0]), ("r_dual", h[1]), ("r_z", h[2])):
+            assert abs(st[key] - ref) <= 2e-3 * max(ref, 1e-8), (b, key, st[key], ref)
+
+
+def test_continue_equals_longer_run(torch_cuda):
+    import torch
+    from paper_1602_01410_amd import binding
+    probs = [_small(64, 48, 5, synth.MASK_BOUNDARY, seed=50), _small(32, 32, 3, synth.MASK_DECIMATE, seed=51)]
+    plan = binding.Plan([desc(p) for p in probs])
+    y, mask, h, lam, mu = device_inputs(probs)
+    x1, _ = plan.run(y, mask, h, lam, mu, 15)
+    x2 = torch.empty_like(x1)
+    plan.cont(lam, mu, 10, x2)
+    torch.cuda.synchronize()
+    for b, p in enumerate(probs):
+        r = oracle_run(p, 25)
+        assert_parity(plan.split(x2)[b].cpu().numpy().astype(np.float64), r["x"], what="continue")
+
+
+def test_error_paths(torch_cuda):
+    import torch
+    from paper_1602_01410_amd import binding
+    p = _small(32, 32, 5, seed=60)
+    plan = binding.Plan([desc(p)])
+    y, mask, h, lam, mu = device_inputs([p])
+    hz = h.clone()
+    hz[0] = 1.0
+    hz[1] = -1.0
+    hz[2:] = 0.0
+    with pytest.raises(binding.DeconvError) as e:
+        plan.run(y, mask, hz, lam, mu, 3)
+    assert e.value.code == 3
+    with pytest.raises(binding.DeconvError) as e:
+        plan.backward(y, mask, h, lam, mu, torch.zeros_like(y))
+    assert e.value.code == 5
+    with pytest.raises(binding.DeconvError) as e:
+        binding.Plan([dict(height=100, width=64, ksize=5)])
+    assert e.value.code == 2
+    with pytest.raises(binding.DeconvError) as e:
+        binding.Plan([dict(height=64, width=64, ksize=4)])
+    assert e.value.code == 2
