@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Throughput of the partial-ADMM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one deconv_admm_run over the workload (blur-spectrum setup, initial
+state, all iterations with the FP64 residual checks), inputs resident in HBM.
+Prints ONE JSON line on stdout; progress goes to stderr.
+
+Default workload: one 1024 x 1024 image (GRF texture + rectangles), 19 x 19
+Gaussian blur sigma 3, unknown boundaries (observed central 1006^2), BSNR 50
+dB, lambda 5e-4, mu 0.02, 500 iterations.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1602_01410_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    from paper_1602_01410_amd import synth
+    if name == "large_1024":
+        p = synth.config_large_1024()
+        return [p], p["iters"], "1x1024^2 GRF+rects, 19x19 Gaussian s=3, unknown boundaries, 500 it"
+    if name == "plain_72":
+        p = synth.config_plain_72()
+        return [p], p["iters"], "1x72^2 rects+ramp, 9x9 box, unknown boundaries, 200 it"
+    if name == "inpaint_2048":
+        p = synth.config_inpaint_2048()
+        return [p], p["iters"], "1x2048^2, 21x21 motion blur, boundaries + 50% missing, 300 it"
+    if name == "batch_256":
+        ps = synth.config_batch()
+        return ps, 200, "256 mixed images 128..1024, Gaussian blurs, half x4 decimated, 200 it"
+    if name == "uniform_16x1024":
+        ps = [synth.problem(1024, 1024, 19, "grf", "gauss", sigma=3.0, bsnr=50.0, lam=5e-4, mu=0.02,
+                            seed=synth.BASE_SEED * 1000 + 500 + b) for b in range(16)]
+        return ps, 500, "16x1024^2 GRF+rects, 19x19 Gaussian s=3, unknown boundaries, 500 it"
+    raise ValueError(name)
+
+
+def descs(problems):
+    return [dict(height=p["M"], width=p["N"], ksize=p["K"], mask_kind=p["mask_kind"], decim=p.get("decim", 1))
+            for p in problems]
+
+
+def to_device(problems):
+    import numpy as np
+    import torch
+    cat = lambda k, dt: torch.from_numpy(np.concatenate([np.asarray(p[k], dt).ravel() for p in problems])).cuda()
+    y = cat("y", np.float32)
+    h = cat("h", np.float32)
+    mask = cat("mask", np.uint8)
+    lam = torch.tensor([p["lam"] for p in problems], dtype=torch.float32, device="cuda")
+    mu = torch.tensor([p["mu"] for p in problems], dtype=torch.float32, device="cuda")
+    return y, mask, h, lam, mu
+
+
+def unobserved_fraction(problems):
+    import numpy as np
+    n = sum(p["M"] * p["N"] for p in problems)
+    k = sum(int(np.count_nonzero(p["mask"])) for p in problems)
+    return (n - k) / n
+
+
+def alg_bytes(problems, unobs):
+    """Algorithmic bytes per launch of each pass (compulsory reads + writes of
+    its own inputs and outputs, each once; halo re-reads excluded).
+    row pass  per pixel: spectra in 16*nh/n' + ytilde 4 + d in 8 + d out 8
+              + spectra out 16*nh/n' + z out 4*(unobserved fraction)
+    col pass  per half-spectrum element: spectra in 16 + blur spectrum 8 + spectra out 16"""
+    row = col = 0.0
+    for p in problems:
+        M, N = p["M"], p["N"]
+        nh = N // 2 + 1
+        row += M * nh * 32.0 + M * N * 20.0
+        col += M * nh * 40.0
+    row += 4.0 * unobs * sum(p["M"] * p["N"] for p in problems)
+    return row, col
+
+
+def read_traffic(name):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % name)
+    if not os.path.exists(path):
+        return None, None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("src_hash") != src_hash():
+        return None, kv.get("kernel")
+    try:
+        return float(kv["bytes_per_launch"]), kv.get("kernel")
+    except (KeyError, ValueError):
+        return None, None
+
+
+def time_runs(plan, inputs, iters, steps, warmup):
+    import torch
+    y, mask, h, lam, mu = inputs
+    x = torch.empty(plan.npx, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        plan.run(y, mask, h, lam, mu, iters, x_out=x)
+    torch.cuda.synchronize()
+    s = plan.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        plan.run(y, mask, h, lam, mu, iters, x_out=x)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(problems, target_s=15.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the
+    workload: the first image, as many iterations as fit in ~target_s."""
+    import numpy as np
+    import oracle
+    p = problems[0]
+    args = (p["y"].astype(np.float64), p["mask"], p["h"].astype(np.float64), float(p["lam"]), float(p["mu"]))
+    t0 = time.perf_counter()
+    oracle.admm_run(*args, 2)
+    t2 = time.perf_counter() - t0
+    n = int(max(2, min(200, target_s / max(t2 / 2.0, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.admm_run(*args, n)
+    t = time.perf_counter() - t0
+    return dict(value=p["M"] * p["N"] * n / t / 1e6, unit="Mpixel*ADMM-iters/s", cores=oracle.num_threads(),
+                kind="oracle", sample="image 0 (%dx%d), %d iterations incl. setup, %.1f s" % (p["M"], p["N"], n, t))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large_1024",
+                    choices=["large_1024", "plain_72", "inpaint_2048", "batch_256", "uniform_16x1024"])
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-compare", action="store_true")
+    ap.add_argument("--no-kernel-times", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1602_01410_amd import binding
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log("generating workload %s" % args.workload)
+    problems, iters, wdesc = workload(args.workload)
+    npx = sum(p["M"] * p["N"] for p in problems)
+    unobs = unobserved_fraction(problems)
+    inputs = to_device(problems)
+    plan = binding.Plan(descs(problems), batched=1, use_graph=1, check_every=args.check_every)
+    log("timing %d steps (+%d warmup), %d images, %d px, %d iterations" % (args.steps, args.warmup,
+                                                                          len(problems), npx, iters))
+    t, wall = time_runs(plan, inputs, iters, args.steps, args.warmup)
+    value = npx * iters * args.steps / t / 1e6
+    ms_step = t / args.steps * 1e3
+    log("value %.1f Mpx*it/s, %.3f ms/step (wall %.3f s)" % (value, ms_step, wall))
+
+    roof = None
+    if not args.no_kernel_times:
+        # per-launch GPU time of each pass, HIP events on the plan's stream
+        pplan = binding.Plan(descs(problems), batched=1, use_graph=0, check_every=args.check_every, profile=1)
+        y, mask, h, lam, mu = inputs
+        pplan.run(y, mask, h, lam, mu, min(iters, 50))
+        pplan.kernel_times()
+        pplan.run(y, mask, h, lam, mu, iters)
+        row_ms, row_n, col_ms, col_n = pplan.kernel_times()
+        rb, cb = alg_bytes(problems, unobs)
+        row_avg, col_avg = row_ms / max(row_n, 1), col_ms / max(col_n, 1)
+        log("row pass %.2f us x %d, column pass %.2f us x %d" % (row_avg * 1e3, row_n, col_avg * 1e3, col_n))
+        if row_ms >= col_ms:
+            kern, avg, ab = "row_kernel", row_avg, rb
+        else:
+            kern, avg, ab = "col_kernel", col_avg, cb
+        achieved = ab / (avg * 1e-3) / 1e9
+        traffic, tk = read_traffic(args.workload)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic if (traffic is not None and tk == kern) else None,
+                "kernel": kern, "launch_us": round(avg * 1e3, 2), "alg_bytes_per_launch": int(ab),
+                "other_pass": {"kernel": "col_kernel" if kern == "row_kernel" else "row_kernel",
+                               "launch_us": round((col_avg if kern == "row_kernel" else row_avg) * 1e3, 2),
+                               "achieved": round((cb / (col_avg * 1e-3) if kern == "row_kernel"
+                                                  else rb / (row_avg * 1e-3)) / 1e9, 1)}}
+        pplan.close()
+
+    extra = {}
+    if args.workload == "large_1024" and not args.no_batch_compare:
+        log("batched vs plain on the 256-image mixed batch")
+        bp, bit, _ = workload("batch_256")
+        bnpx = sum(p["M"] * p["N"] for p in bp)
+        binp = to_device(bp)
+        res = {}
+        for mode, kw in (("batched_graph", dict(batched=1, use_graph=1)),
+                         ("plain", dict(batched=0, use_graph=0)),
+                         ("plain_graph", dict(batched=0, use_graph=1))):
+            pl = binding.Plan(descs(bp), check_every=args.check_every, **kw)
+            tt, _ = time_runs(pl, binp, bit, 1, 1)
+            res[mode] = bnpx * bit / tt / 1e6
+            log("  %s: %.1f Mpx*it/s" % (mode, res[mode]))
+            pl.close()
+            torch.cuda.empty_cache()
+        extra["batch_256"] = {"mpx_it_s": {k: round(v, 1) for k, v in res.items()},
+                              "batched_over_plain": round(res["batched_graph"] / res["plain"], 2)}
+        del binp
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        cpu = cpu_baseline(problems)
+        cpu["value"] = round(cpu["value"], 4)
+        log("  %s" % cpu)
+
+    out = {"metric": "Mpixel*ADMM-iters/s", "value": round(value, 2), "unit": "Mpixel*ADMM-iters/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "description": wdesc, "images": len(problems), "pixels": npx,
+                      "iters": iters, "check_every": args.check_every, "unobserved_fraction": round(unobs, 4)},
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

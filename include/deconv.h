@@ -97,6 +97,8 @@ typedef struct {
   int32_t ckpt_every;   /* keep the state every k iterations for the backward
                            pass (0 = no backward support) */
   int32_t max_iters;    /* upper bound on iters, sizes the checkpoint store */
+  int32_t profile;      /* 1: bracket every row / column pass launched outside a
+                           graph with HIP events (read by deconv_plan_kernel_times) */
 } deconv_options;
 
 typedef struct {
@@ -186,6 +188,13 @@ deconv_status deconv_blur_spectrum(deconv_plan p, const float* h, float* spectru
    transformed in place.  Same size rules as images.  Runs on `stream`. */
 deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* data,
                           int32_t inverse, void* stream);
+
+/* With opt.profile = 1: GPU time of the row and column passes launched since
+   the last call, from HIP events on the plan's stream (synchronises).
+   out[0] = row-pass milliseconds, out[1] = row-pass launches,
+   out[2] = column-pass milliseconds, out[3] = column-pass launches.
+   Passes replayed inside a graph are not bracketed. */
+deconv_status deconv_plan_kernel_times(deconv_plan p, double* out);
 
 const char* deconv_status_str(deconv_status s);
 

@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("check_every", ctypes.c_int32),
                 ("tol_primal", ctypes.c_double), ("tol_dual", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("batched", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("max_iters", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -45,7 +46,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_create",
            "deconv_plan_destroy", "deconv_admm_run", "deconv_admm_continue", "deconv_state_export",
            "deconv_state_import", "deconv_admm_backward", "deconv_blur_spectrum", "deconv_fft2",
-           "deconv_status_str")
+           "deconv_plan_kernel_times", "deconv_status_str")
 
 _lib = None
 
@@ -72,6 +73,7 @@ def lib():
         L.deconv_admm_backward.argtypes = [P, P, P, P, P, P, P, P, P, P]
         L.deconv_blur_spectrum.argtypes = [P, P, P]
         L.deconv_fft2.argtypes = [I32, I32, I32, P, I32, P]
+        L.deconv_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
         L.deconv_status_str.argtypes = [I32]
         L.deconv_status_str.restype = ctypes.c_char_p
         for f in EXPORTS:
@@ -199,6 +201,13 @@ class Plan:
         d = torch.empty(2 * self.npx, dtype=torch.float32, device=device)
         _check(lib().deconv_state_export(self.handle, _ptr(yt), _ptr(v), _ptr(d)), "state_export")
         return yt, v, d
+
+    def kernel_times(self):
+        """(row_ms, row_launches, col_ms, col_launches) since the last call
+        (plan created with profile=1; launches outside graphs only)."""
+        out = (ctypes.c_double * 4)()
+        _check(lib().deconv_plan_kernel_times(self.handle, out), "kernel_times")
+        return tuple(out)
 
     def state_import(self, h, mu, yt, v, d):
         _check(lib().deconv_state_import(self.handle, _ptr(h), _ptr(mu), _ptr(yt), _ptr(v), _ptr(d)),

@@ -255,6 +255,10 @@ struct deconv_plan_s {
   int last_iters = 0;   // iterations of the last run (for the backward)
   bool ck_valid = false;
 
+  // per-launch timing (opt.profile): event pairs around row / column passes
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_row, ev_col;
+  std::vector<hipEvent_t> ev_pool;
+
   // graph cache: one executable graph per (check period, buffer parity,
   // argument pointers); replayed for every whole check period of a run
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
@@ -413,6 +417,7 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->batched = 1;
   opt->ckpt_every = 0;
   opt->max_iters = 0;
+  opt->profile = 0;
   return DECONV_OK;
 }
 
@@ -434,6 +439,9 @@ extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
   if (!p) return DECONV_ERR_INVALID_ARG;
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (auto& e : p->ev_row) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : p->ev_col) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->own_ws && p->ws) (void)hipFree(p->ws);
   delete p;
   return DECONV_OK;
@@ -616,8 +624,38 @@ static ColArgs col_args(deconv_plan_s* p, const float* mu) {
   return a;
 }
 
+static hipEvent_t take_event(deconv_plan_s* p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// bracket a pass with events when profiling (never inside a capture)
+struct PassTimer {
+  deconv_plan_s* p;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* dst;
+  hipEvent_t a = nullptr;
+  PassTimer(deconv_plan_s* p_, std::vector<std::pair<hipEvent_t, hipEvent_t>>* d) : p(p_), dst(d) {
+    if (p->opt.profile && p->ls == p->stream) {
+      a = take_event(p);
+      if (a) (void)hipEventRecord(a, p->ls);
+    }
+  }
+  ~PassTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(p);
+    if (b && hipEventRecord(b, p->ls) == hipSuccess) dst->emplace_back(a, b);
+  }
+};
+
 // launch the row pass over every image (batched) or image by image
 static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
+  PassTimer timer(p, &p->ev_row);
   if (p->opt.batched) {
     for (auto& g : p->row_groups) {
       a.tiles = p->d_tiles + g.tile0;
@@ -634,6 +672,7 @@ static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
 }
 
 static deconv_status launch_cols(deconv_plan_s* p, ColArgs a) {
+  PassTimer timer(p, &p->ev_col);
   if (p->opt.batched) {
     for (auto& g : p->col_groups) {
       a.tiles = p->d_tiles + g.tile0;
@@ -924,6 +963,26 @@ extern "C" deconv_status deconv_fft2(int32_t count, int32_t height, int32_t widt
 }
 
 #include "backward_host.inc"
+
+extern "C" deconv_status deconv_plan_kernel_times(deconv_plan p, double* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  double ms[2] = {0.0, 0.0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* lists[2] = {&p->ev_row, &p->ev_col};
+  for (int k = 0; k < 2; ++k) {
+    for (auto& e : *lists[k]) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+      ms[k] += t;
+      p->ev_pool.push_back(e.first);
+      p->ev_pool.push_back(e.second);
+    }
+    out[2 * k] = ms[k];
+    out[2 * k + 1] = (double)lists[k]->size();
+    lists[k]->clear();
+  }
+  return DECONV_OK;
+}
 
 extern "C" const char* deconv_status_str(deconv_status s) {
   switch (s) {
