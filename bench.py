@@ -165,6 +165,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-compare", action="store_true")
     ap.add_argument("--no-kernel-times", action="store_true")
+    ap.add_argument("--iters", type=int, default=0, help="override the workload's iteration count")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
@@ -174,9 +177,22 @@ def main():
     from paper_1602_01410_amd import binding
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the kernel traffic figures
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4}), flush=True)
+        return
 
     log("generating workload %s" % args.workload)
     problems, iters, wdesc = workload(args.workload)
+    if args.iters:
+        iters = args.iters
     npx = sum(p["M"] * p["N"] for p in problems)
     unobs = unobserved_fraction(problems)
     inputs = to_device(problems)

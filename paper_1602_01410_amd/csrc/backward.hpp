@@ -79,14 +79,13 @@ template <int L>
 __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r0, float2* lds) {
   constexpr int RT = rt_for(L);
   constexpr int LS = lstride(L);
-  constexpr int KP = ((RT + 1) * L + kNT - 1) / kNT;
+  constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;
   const ImgMeta mt = a.meta[img];
   const int M = mt.m;
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   float2* buf = lds;
-  float2* tw = lds + (RT + 2) * LS;
-  load_twiddles<L, kNT>(tw, a.tw + mt.twr);
+  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 2) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
   const int npx = (nr + 1) * L;
@@ -96,28 +95,14 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
 
   if (a.mode != BWD_START) {
     // finish reverse step: rb + i H rb on rows r0-1 .. r0+nr
-    const float4* __restrict__ sin = a.spec_in + mt.sp;
-    const int nl = nr + 2;
-    const int tot = nb * nl * C;
-    for (int q = threadIdx.x; q < tot; q += kNT) {
-      const int c = q & (C - 1);
-      const int t2 = q >> logC;
-      const int l = t2 % nl, blk = t2 / nl;
-      const int kx = blk * C + c;
-      if (kx >= nh) continue;
-      const int i = wrapi(r0 - 1 + l, M);
-      const float4 v = sin[((long long)blk * M + i) * C + c];
-      float2* line = buf + l * LS;
-      line[lpad(kx)] = make_float2(v.x - v.w, v.y + v.z);
-      if (kx >= 1 && kx <= L - nh) line[lpad(L - kx)] = make_float2(v.x + v.w, v.z - v.y);
-    }
+    gather_rows<L, RT + 2>(a.spec_in + mt.sp, buf, M, r0, nr + 2, nh, nb, C, logC);
     __syncthreads();
-    fft_lines<L, true, kNT, RT + 2>(buf, nl, tw);
+    fft_lines<L, true, kNTR, RT + 2>(buf, nr + 2, tw);
   }
 
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       const int i = wrapi(r0 - 1 + l, M);
@@ -170,7 +155,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   }
 
   if (a.mode != BWD_END) {
-    __shared__ double red[3 * (kNT / 64)];
+    __shared__ double red[3 * (kNTR / 64)];
     double ls = lsum, z0 = 0.0, z1 = 0.0;
     block_sum3(ls, z0, z1, red);
     if (threadIdx.x == 0) a.lam_part[mt.rt0 + r0 / RT] += ls / (double)mu;
@@ -182,7 +167,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       buf[l * LS + lpad(j)] = ureg[k];
@@ -191,7 +176,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       if (l >= 1) {
@@ -207,33 +192,21 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       if (l >= 1) buf[l * LS + lpad(j)] = ureg[k];
     }
   }
   __syncthreads();
-  fft_lines<L, false, kNT, RT>(buf + LS, nr, tw);
-  float4* __restrict__ sout = a.spec_out + mt.sp;
-  const int tot2 = nb * nr * C;
-  for (int q = threadIdx.x; q < tot2; q += kNT) {
-    const int c = q & (C - 1);
-    const int t2 = q >> logC;
-    const int l = t2 % nr, blk = t2 / nr;
-    const int kx = blk * C + c;
-    if (kx >= nh) continue;
-    const float2 cf = buf[(l + 1) * LS + lpad(kx)];
-    const float2 cm = buf[(l + 1) * LS + lpad(kx == 0 ? 0 : L - kx)];
-    sout[((long long)blk * M + r0 + l) * C + c] =
-        make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
-  }
+  fft_lines<L, false, kNTR, RT>(buf + LS, nr, tw);
+  split_store<L, RT>(a.spec_out + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
 }
 
 template <int L>
-__global__ void __launch_bounds__(kNT) bwd_row_kernel(BwdRowArgs a) {
+__global__ void __launch_bounds__(kNTR) bwd_row_kernel(BwdRowArgs a) {
   extern __shared__ float2 lds[];
-  const int4 t = a.tiles[blockIdx.x];
+  const int4 t = a.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   bwd_row_tile<L>(a, t.x, t.y, lds);
 }
 
@@ -243,18 +216,17 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
   constexpr int LS = lstride(L);
   const ImgMeta mt = a.meta[img];
   float2* buf = lds;
-  float2* tw = lds + 2 * C * LS;
-  load_twiddles<L, kNT>(tw, a.tw + mt.twc);
+  const float2* tw = twiddle_table<L, kNTC>(lds + 2 * C * LS, a.tw + mt.twc);
   const long long base = mt.sp + (long long)blk * L * C;
   const float4* __restrict__ sin = a.spec_in + base;
-  for (int q = threadIdx.x; q < L * C; q += kNT) {
+  for (int q = threadIdx.x; q < L * C; q += kNTC) {
     const int i = q / C, c = q - i * C;
     const float4 v = sin[q];
     buf[(2 * c) * LS + lpad(i)] = make_float2(v.x, v.y);
     buf[(2 * c + 1) * LS + lpad(i)] = make_float2(v.z, v.w);
   }
   __syncthreads();
-  fft_lines<L, false, kNT, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, false, kNTC, 2 * C>(buf, 2 * C, tw);
   const float mu = a.mu[img];
   const float mn = (float)L * (float)mt.n;
   const float scale = 1.0f / mn;
@@ -263,7 +235,7 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
   const float* __restrict__ dh2 = dv2 + L;
   const float4* __restrict__ fs = a.fwd_spec + base;
   float2* S = a.S + mt.hh + (long long)blk * L * C;
-  for (int q = threadIdx.x; q < L * C; q += kNT) {
+  for (int q = threadIdx.x; q < L * C; q += kNTC) {
     const int ky = q / C, c = q - ky * C;
     const int kx = blk * C + c;
     const float2 XB = buf[(2 * c) * LS + lpad(ky)];
@@ -274,7 +246,8 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
       const float den = Hk.x * Hk.x + Hk.y * Hk.y + mu * (dh2[kx] + dv2[ky]);
       // xb_hat = XB + conj(H) QB ; rb_hat = xb_hat / den
       const float2 xbh = make_float2(XB.x + Hk.x * QB.x + Hk.y * QB.y, XB.y + Hk.x * QB.y - Hk.y * QB.x);
-      const float2 rb = make_float2(xbh.x / den, xbh.y / den);
+      const float rden = frcp(den);
+      const float2 rb = make_float2(xbh.x * rden, xbh.y * rden);
       const float4 f = fs[q];
       const float2 Y = make_float2(f.x, f.y);
       const float2 X = make_float2(f.z * mn, f.w * mn);
@@ -291,9 +264,9 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
     buf[(2 * c + 1) * LS + lpad(ky)] = HR;
   }
   __syncthreads();
-  fft_lines<L, true, kNT, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
   float4* __restrict__ sout = a.spec_out + base;
-  for (int q = threadIdx.x; q < L * C; q += kNT) {
+  for (int q = threadIdx.x; q < L * C; q += kNTC) {
     const int i = q / C, c = q - i * C;
     const float2 X = buf[(2 * c) * LS + lpad(i)];
     const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
@@ -302,7 +275,7 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
 }
 
 template <int L>
-__global__ void __launch_bounds__(kNT) bwd_col_kernel(BwdColArgs a) {
+__global__ void __launch_bounds__(kNTC) bwd_col_kernel(BwdColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   bwd_col_tile<L>(a, t.x, t.y, lds);

@@ -71,14 +71,14 @@ static size_t col_lds_bytes(int L) {
 }
 
 template <typename K>
-static hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void** args) {
-  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(kNT), args, lds, s);
+static hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void** args, int nt = kNT) {
+  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(nt), args, lds, s);
 }
 
 static hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a) {
   void* args[] = {&a};
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(row_kernel<n>, grid, lds, s, args);
+#define DCV_CASE(n) case n: return launch_lds(row_kernel<n>, grid, lds, s, args, kNTR);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
@@ -87,7 +87,7 @@ static hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs
 static hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a) {
   void* args[] = {&a};
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(col_kernel<n>, grid, lds, s, args);
+#define DCV_CASE(n) case n: return launch_lds(col_kernel<n>, grid, lds, s, args, kNTC);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
@@ -96,7 +96,7 @@ static hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs
 static hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a) {
   void* args[] = {&a};
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(bwd_row_kernel<n>, grid, lds, s, args);
+#define DCV_CASE(n) case n: return launch_lds(bwd_row_kernel<n>, grid, lds, s, args, kNTR);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
@@ -105,7 +105,7 @@ static hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, Bwd
 static hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a) {
   void* args[] = {&a};
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(bwd_col_kernel<n>, grid, lds, s, args);
+#define DCV_CASE(n) case n: return launch_lds(bwd_col_kernel<n>, grid, lds, s, args, kNTC);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
@@ -222,7 +222,7 @@ struct deconv_plan_s {
   int* nonfinite = nullptr;
   int* iters_done = nullptr;
   double* res = nullptr;
-  double* mean = nullptr;
+  double* mean = nullptr;     // per image and row block: observed sum, count
   long long* goff = nullptr;
   long long* hoff = nullptr;
   float2* hsum = nullptr;     // DC term of each spectrum (host check)
@@ -290,7 +290,7 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     if (d.ksize < 1 || d.ksize % 2 == 0) return DECONV_ERR_UNSUPPORTED_SIZE;
     if (2 * (d.ksize / 2) >= std::min(d.height, d.width)) return DECONV_ERR_UNSUPPORTED_SIZE;
     if (d.mask_kind < 0 || d.mask_kind > 2) return DECONV_ERR_INVALID_ARG;
-    if (d.mask_kind == DECONV_MASK_DECIMATE && d.decim < 1) return DECONV_ERR_INVALID_ARG;
+    if (d.mask_kind == DECONV_MASK_DECIMATE && (d.decim < 1 || d.decim > 2048)) return DECONV_ERR_INVALID_ARG;
     if ((int)row_lds_bytes(d.width) > max_lds_bytes() || (int)col_lds_bytes(d.height) > max_lds_bytes())
       return DECONV_ERR_UNSUPPORTED_SIZE;
   }
@@ -310,6 +310,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     ImgMeta& m = p->meta[b];
     m.m = d.height; m.n = d.width; m.b = d.ksize / 2;
     m.mask_kind = d.mask_kind; m.decim = d.mask_kind == DECONV_MASK_DECIMATE ? d.decim : 1;
+    m.dmagic = m.decim > 1 ? (unsigned)((1ull << 32) / (unsigned)m.decim) + 1u : 0u;
     m.nh = d.width / 2 + 1;
     m.C = c_for(d.height);
     m.logC = 0; while ((1 << m.logC) < m.C) ++m.logC;
@@ -375,7 +376,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   lay.off_nonf = take(sizeof(int) * B);
   lay.off_itd = take(sizeof(int) * B);
   lay.off_res = take(sizeof(double) * 3 * B);
-  lay.off_mean = take(sizeof(double) * B);
+  lay.off_mean = take(sizeof(double) * 2 * kMeanBlocks * B);
   lay.off_goff = take(sizeof(long long) * B);
   lay.off_hoff = take(sizeof(long long) * B);
   lay.off_hsum = take(sizeof(float2) * B);
@@ -569,7 +570,8 @@ static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* ful
   float2* grid = reinterpret_cast<float2*>(p->specB);
   const int B = p->batch;
   int gx = 64;
-  hipLaunchKernelGGL(embed_psf_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, grid, p->goff);
+  HIPCHK(hipMemsetAsync(grid, 0, sizeof(float4) * (size_t)p->total_sp, s));
+  hipLaunchKernelGGL(embed_psf_kernel, dim3(B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, grid, p->goff);
   HIPCHK(hipGetLastError());
   for (int b = 0; b < B; ++b) {
     const ImgMeta& m = p->meta[b];
@@ -884,11 +886,12 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   p->ck_valid = false;
   STCHK(setup_spectrum(p, h, nullptr));
   STCHK(reset_counters(p));
-  hipLaunchKernelGGL(observed_mean_kernel, dim3(p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean);
+  hipLaunchKernelGGL(observed_sum_kernel, dim3(kMeanBlocks, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask,
+                     p->mean);
   HIPCHK(hipGetLastError());
   p->cur_d = 0;
-  hipLaunchKernelGGL(init_state_kernel, dim3(64, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean, p->yt,
-                     p->v, p->dbuf[0]);
+  hipLaunchKernelGGL(init_state_kernel, dim3(256, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean,
+                     kMeanBlocks, p->yt, p->v, p->dbuf[0]);
   HIPCHK(hipGetLastError());
   STCHK(prologue_from_state(p, mu));
   STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));

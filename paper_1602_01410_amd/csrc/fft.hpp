@@ -36,9 +36,13 @@ struct RadixPlan {
   static_assert((1 << a) * pow3(c3) == L, "length must be 2^a 3^c");
 };
 
-// LDS layout of one line: one padding slot every 32 complex values spreads
+// LDS layout of one line: one padding slot every 16 complex values spreads
 // the power-of-two strides of the Stockham writes over the banks.
-__host__ __device__ constexpr int lpad(int i) { return i + (i >> 5); }
+#ifndef DCV_PAD_SHIFT
+#define DCV_PAD_SHIFT 4
+#endif
+constexpr int kPadShift = DCV_PAD_SHIFT;
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> kPadShift); }
 __host__ __device__ constexpr int lstride(int L) { return lpad(L) + 1; }
 
 // ---------------------------------------------------------------------------
@@ -146,6 +150,39 @@ template <bool INV> struct Dft<16, INV> {
 };
 
 // ---------------------------------------------------------------------------
+// v[k] *= w^k with w = exp(-+2 pi i jm S / L), k = 1..R-1.  The powers w, w^2,
+// w^4, w^8 come from the table (exact up to the float rounding of the table);
+// the others are products of at most three of them.
+// ---------------------------------------------------------------------------
+template <int R, int S, bool INV>
+__device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* tw) {
+  float2 w[R];
+  w[1] = tw[jm * S];
+  if constexpr (R > 2) w[2] = tw[2 * jm * S];
+  if constexpr (R == 3) {
+  } else if constexpr (R >= 4) {
+    w[3] = cmul(w[1], w[2]);
+    if constexpr (R >= 8) {
+      w[4] = tw[4 * jm * S];
+      w[5] = cmul(w[4], w[1]);
+      w[6] = cmul(w[4], w[2]);
+      w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (R >= 16) {
+      w[8] = tw[8 * jm * S];
+#pragma unroll
+      for (int k = 9; k < 16; ++k) w[k] = cmul(w[8], w[k - 8]);
+    }
+  }
+#pragma unroll
+  for (int k = 1; k < R; ++k) {
+    float2 t = w[k];
+    if (INV) t.y = -t.y;
+    v[k] = cmul(v[k], t);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // one Stockham pass over `nlines` lines of length L stored in LDS
 // (line q at buf + q * lstride(L)); NT threads cooperate, each takes up to
 // MAXB butterflies.  tw is the LDS table exp(-2 pi i t / L), t < L.
@@ -166,7 +203,11 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
       const int line = idx / NB, j = idx - line * NB;
       const float2* src = buf + line * LS;
 #pragma unroll
-      for (int k = 0; k < R; ++k) v[q][k] = src[lpad(j + k * NB)];
+      for (int k = 0; k < R; ++k) {
+        // a stride that is a multiple of the padding period pads uniformly
+        if constexpr (NB % (1 << kPadShift) == 0) v[q][k] = src[lpad(j) + k * lpad(NB)];
+        else v[q][k] = src[lpad(j + k * NB)];
+      }
     }
   }
   __syncthreads();
@@ -176,19 +217,15 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
     if (idx < total) {
       const int line = idx / NB, j = idx - line * NB;
       const int jm = j % NS;
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int k = 1; k < R; ++k) {
-          float2 w = tw[jm * k * S];
-          if (INV) w.y = -w.y;
-          v[q][k] = cmul(v[q][k], w);
-        }
-      }
+      if constexpr (NS > 1) apply_twiddles<R, S, INV>(v[q], jm, tw);
       Dft<R, INV>::run(v[q]);
       float2* dst = buf + line * LS;
       const int base = (j / NS) * NS * R + jm;
 #pragma unroll
-      for (int k = 0; k < R; ++k) dst[lpad(base + k * NS)] = v[q][k];
+      for (int k = 0; k < R; ++k) {
+        if constexpr (NS % (1 << kPadShift) == 0) dst[lpad(base) + k * lpad(NS)] = v[q][k];
+        else dst[lpad(base + k * NS)] = v[q][k];
+      }
     }
   }
   __syncthreads();

@@ -32,19 +32,54 @@
 
 namespace dcv {
 
-constexpr int kNT = 256;   // threads per workgroup of every ADMM kernel
+#ifndef DCV_NT
+#define DCV_NT 256
+#endif
+#ifndef DCV_ROW_PIX
+#define DCV_ROW_PIX 4096
+#endif
+#ifndef DCV_COL_ELEMS
+#define DCV_COL_ELEMS 1024
+#endif
+#ifndef DCV_NT_ROW
+#define DCV_NT_ROW 512
+#endif
+#ifndef DCV_NT_COL
+#define DCV_NT_COL 256
+#endif
+constexpr int kNT = DCV_NT;       // threads per workgroup of the setup / reduction kernels
+constexpr int kNTR = DCV_NT_ROW;  // threads per workgroup of the row passes
+constexpr int kNTC = DCV_NT_COL;  // threads per workgroup of the column passes
 
-// rows per row-pass tile and columns per column-pass block, by line length
+// rows per row-pass tile (about DCV_ROW_PIX pixels, at least 2 rows) and
+// columns per column-pass block (a power of two, about DCV_COL_ELEMS / L)
 __host__ __device__ constexpr int rt_for(int L) {
-  return 4096 / L < 2 ? 2 : (4096 / L > 32 ? 32 : 4096 / L);
+  return DCV_ROW_PIX / L < 2 ? 2 : (DCV_ROW_PIX / L > 32 ? 32 : DCV_ROW_PIX / L);
 }
 __host__ __device__ constexpr int c_for(int L) {
   int c = 1;
-  while (c * 2 <= 2048 / L && c * 2 <= 16) c *= 2;
+  while (c * 2 <= DCV_COL_ELEMS / L && c * 2 <= 16) c *= 2;
   return c;
 }
-__host__ __device__ constexpr int row_lds_elems(int L) { return (rt_for(L) + 2) * lstride(L) + L; }
-__host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + L; }
+// Twiddle tables are read from LDS (copied per workgroup) or straight from
+// the global table through the L1 cache.
+#ifndef DCV_TW_GLOBAL
+#define DCV_TW_GLOBAL 1
+#endif
+constexpr int kTwLds = DCV_TW_GLOBAL ? 0 : 1;
+__host__ __device__ constexpr int row_lds_elems(int L) { return (rt_for(L) + 2) * lstride(L) + kTwLds * L; }
+__host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLds * L; }
+
+// the twiddle table a workgroup uses for length L (caller synchronises)
+template <int L, int NT>
+__device__ __forceinline__ const float2* twiddle_table(float2* lds_tw, const float2* __restrict__ glob) {
+  if constexpr (kTwLds) {
+    load_twiddles<L, NT>(lds_tw, glob);
+    return lds_tw;
+  } else {
+    return glob;
+  }
+}
 
 struct ImgMeta {
   int m, n;            // m' (rows), n' (columns)
@@ -53,7 +88,7 @@ struct ImgMeta {
   int nh, C, logC, nb; // half-spectrum columns, block width (power of 2), blocks
   int rt;              // rows per row tile
   int nrt;             // row tiles
-  int pad_;
+  unsigned dmagic;     // floor(2^32 / decim) + 1: exact x / decim for x < 2^11
   long long px;        // offset of the image in pixel arrays
   long long sp;        // offset in half-spectrum buffers (float4 units)
   long long hh;        // offset in the blur half spectrum (float2 units)
@@ -98,15 +133,39 @@ struct ColArgs {
   const int* done;
 };
 
+// x % s == 0 for 0 <= x < 2^11 and 1 < s <= 2^11, with magic = floor(2^32/s) + 1
+__device__ __forceinline__ bool divisible(int x, int s, unsigned magic) {
+  const unsigned q = __umulhi((unsigned)x, magic);
+  return (unsigned)x == q * (unsigned)s;
+}
+
 __device__ __forceinline__ bool observed(const ImgMeta& mt, const uint8_t* __restrict__ mask,
                                          int i, int j) {
-  if (mt.mask_kind == 1) return mask[mt.px + (long long)i * mt.n + j] != 0;
+  if (mt.mask_kind == 1) return mask[mt.px + (i * mt.n + j)] != 0;
   const bool in_c = i >= mt.b && i < mt.m - mt.b && j >= mt.b && j < mt.n - mt.b;
-  if (mt.mask_kind == 2) return in_c && ((i - mt.b) % mt.decim) == 0 && ((j - mt.b) % mt.decim) == 0;
+  if (mt.mask_kind == 2 && mt.decim > 1)
+    return in_c && divisible(i - mt.b, mt.decim, mt.dmagic) && divisible(j - mt.b, mt.decim, mt.dmagic);
   return in_c;
 }
 
 __device__ __forceinline__ int wrapi(int i, int M) { return i < 0 ? i + M : (i >= M ? i - M : i); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remap the block index so that each XCD gets a contiguous range of
+// tiles: neighbouring row tiles (which share halo rows) then meet in the
+// same L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  constexpr int kXcd = 8;
+  const int q = nblocks / kXcd, r = nblocks % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// reciprocal with one Newton step (error below 1 ulp of the exact division)
+__device__ __forceinline__ float frcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return r * (2.0f - x * r);
+}
 
 // sum three doubles over the workgroup; result valid in thread 0
 __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* scratch) {
@@ -131,18 +190,87 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // ---------------------------------------------------------------------------
 // row pass
 // ---------------------------------------------------------------------------
+
+// Gather X + iQ for lines 0..nl-1 (image rows r0-1 .. r0+nl-2, periodic) from
+// the tiled half spectra into LDS, completing the other half by Hermitian
+// symmetry.  All loads of a thread are issued before any LDS write.
+template <int L, int NLMAX>
+__device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nl,
+                                            int nh, int nb, int C, int logC) {
+  constexpr int LS = lstride(L);
+  constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
+  constexpr int NQ = (NLMAX * NBC_MAX + kNTR - 1) / kNTR;
+  float4 g[NQ];
+  int dst[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTR;
+    const int c = q & (C - 1);
+    const int t2 = q >> logC;
+    const int l = t2 % NLMAX, blk = t2 / NLMAX;
+    const int kx = blk * C + c;
+    dst[k] = -1;
+    if (l < nl && blk < nb && kx < nh) {
+      int i = r0 - 1 + l;
+      i = i < 0 ? i + M : (i >= M ? i - M : i);
+      g[k] = sin[(blk * M + i) * C + c];
+      dst[k] = l * LS + kx;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    if (dst[k] >= 0) {
+      const int l = dst[k] / LS, kx = dst[k] - l * LS;
+      const float4 v = g[k];
+      float2* line = buf + l * LS;
+      line[lpad(kx)] = make_float2(v.x - v.w, v.y + v.z);
+      if (kx >= 1 && kx <= L - nh) line[lpad(L - kx)] = make_float2(v.x + v.w, v.z - v.y);
+    }
+  }
+}
+
+// Split C = F(a) + i F(b) of lines 1..nr into the half spectra of the real
+// signals a, b and store them in the tiled layout.
+template <int L, int RT>
+__device__ __forceinline__ void split_store(float4* __restrict__ sout, const float2* buf, int M, int r0, int nr,
+                                            int nh, int nb, int C, int logC) {
+  constexpr int LS = lstride(L);
+  constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
+  constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTR;
+    const int c = q & (C - 1);
+    const int t2 = q >> logC;
+    const int l = t2 % RT, blk = t2 / RT;
+    const int kx = blk * C + c;
+    if (l < nr && blk < nb && kx < nh) {
+      const float2 cf = buf[(l + 1) * LS + lpad(kx)];
+      const float2 cm = buf[(l + 1) * LS + lpad(kx == 0 ? 0 : L - kx)];
+      sout[(blk * M + r0 + l) * C + c] =
+          make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
+    }
+  }
+}
+
 template <int L>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
   constexpr int RT = rt_for(L);
   constexpr int LS = lstride(L);
-  constexpr int KP = ((RT + 1) * L + kNT - 1) / kNT;  // pixels per thread (own rows + 1 halo)
+  constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;  // pixels per thread (own rows + 1 halo)
   const ImgMeta mt = a.meta[img];
   const int M = mt.m;
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
+  // image-local bases (uniform) with 32-bit offsets below
+  const float2* __restrict__ d_in = a.d_in + mt.px;
+  float2* __restrict__ d_out = a.d_out + mt.px;
+  float* __restrict__ yt = a.yt + mt.px;
+  float2* __restrict__ vst = a.v + mt.px;
+  float* __restrict__ x_out = a.x_out ? a.x_out + mt.px : nullptr;
+  float2* __restrict__ u_out = a.u_out ? a.u_out + mt.px : nullptr;
   float2* buf = lds;
-  float2* tw = lds + (RT + 2) * LS;
-  load_twiddles<L, kNT>(tw, a.tw + mt.twr);
+  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 2) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
   const int npx = (nr + 1) * L;   // rows r0-1 .. r0+nr-1
@@ -151,29 +279,28 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
   if (a.mode == ROW_ITER) {
-    // gather X + iQ for rows r0-1 .. r0+nr (Hermitian completion of the half spectra)
-    const float4* __restrict__ sin = a.spec_in + mt.sp;
-    const int nl = nr + 2;
-    const int tot = nb * nl * C;
-    for (int q = threadIdx.x; q < tot; q += kNT) {
-      const int c = q & (C - 1);
-      const int t2 = q >> logC;
-      const int l = t2 % nl, blk = t2 / nl;
-      const int kx = blk * C + c;
-      if (kx >= nh) continue;
-      const int i = wrapi(r0 - 1 + l, M);
-      const float4 v = sin[((long long)blk * M + i) * C + c];
-      float2* line = buf + l * LS;
-      line[lpad(kx)] = make_float2(v.x - v.w, v.y + v.z);
-      if (kx >= 1 && kx <= L - nh) line[lpad(L - kx)] = make_float2(v.x + v.w, v.z - v.y);
+    gather_rows<L, RT + 2>(a.spec_in + mt.sp, buf, M, r0, nr + 2, nh, nb, C, logC);
+    // state loads for the epilogue, issued before the transform
+    float2 dd[KP];
+    float yo[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = threadIdx.x + k * kNTR;
+      if (p < npx) {
+        const int l = p / L, j = p - l * L;
+        const int i = wrapi(r0 - 1 + l, M);
+        const int pix = i * L + j;
+        dd[k] = d_in[pix];
+        if (l >= 1) yo[k] = yt[pix];
+      }
     }
     __syncthreads();
-    fft_lines<L, true, kNT, RT + 2>(buf, nl, tw);
+    fft_lines<L, true, kNTR, RT + 2>(buf, nr + 2, tw);
 
     // epilogue: z-step, TV prox, dual update for rows r0-1 .. r0+nr-1
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = threadIdx.x + k * kNT;
+      const int p = threadIdx.x + k * kNTR;
       if (p < npx) {
         const int l = p / L, j = p - l * L;
         const int i = wrapi(r0 - 1 + l, M);
@@ -181,32 +308,30 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
         const float x = c0.x;
         const float xr = buf[l * LS + lpad(j + 1 == L ? 0 : j + 1)].x;
         const float xd = buf[(l + 1) * LS + lpad(j)].x;
-        const long long pix = mt.px + (long long)i * L + j;
-        const float2 dd = a.d_in[pix];
-        const float uh = xr - x + dd.x, uv = xd - x + dd.y;
+        const int pix = i * L + j;
+        const float uh = xr - x + dd[k].x, uv = xd - x + dd[k].y;
         const float nrm = sqrtf(uh * uh + uv * uv);
-        const float s = nrm > tau ? (nrm - tau) / nrm : 0.f;
+        const float s = nrm > tau ? 1.0f - tau * frcp(nrm) : 0.f;
         const float vh = s * uh, vv = s * uv;
         const float dh = uh - vh, dv = uv - vv;
         wreg[k] = make_float2(vh - dh, vv - dv);
         if (l >= 1) {
-          a.d_out[pix] = make_float2(dh, dv);
-          rd += (dh - dd.x) * (dh - dd.x) + (dv - dd.y) * (dv - dd.y);
+          d_out[pix] = make_float2(dh, dv);
+          rd += (dh - dd[k].x) * (dh - dd[k].x) + (dv - dd[k].y) * (dv - dd[k].y);
           if (a.check) {
-            const float2 vo = a.v[pix];
+            const float2 vo = vst[pix];
             rv += (vh - vo.x) * (vh - vo.x) + (vv - vo.y) * (vv - vo.y);
           }
-          if (a.store_v) a.v[pix] = make_float2(vh, vv);
-          const float yo = a.yt[pix];
-          float yn = yo;
+          if (a.store_v) vst[pix] = make_float2(vh, vv);
+          float yn = yo[k];
           if (!observed(mt, a.mask, i, j)) {
-            yn = yo + a.alpha * (c0.y - yo);
-            a.yt[pix] = yn;
-            rz += (yn - yo) * (yn - yo);
+            yn = yo[k] + a.alpha * (c0.y - yo[k]);
+            yt[pix] = yn;
+            rz += (yn - yo[k]) * (yn - yo[k]);
           }
           ynew[k] = yn;
-          if (a.store_x) a.x_out[pix] = x;
-          if (a.u_out) a.u_out[pix] = make_float2(uh, uv);
+          if (a.store_x) x_out[pix] = x;
+          if (u_out) u_out[pix] = make_float2(uh, uv);
         }
       }
     }
@@ -214,23 +339,23 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
     // ROW_STATE: start from a stored state (v, d, ytilde)
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = threadIdx.x + k * kNT;
+      const int p = threadIdx.x + k * kNTR;
       if (p < npx) {
         const int l = p / L, j = p - l * L;
         const int i = wrapi(r0 - 1 + l, M);
-        const long long pix = mt.px + (long long)i * L + j;
-        const float2 vv = a.v[pix], dd = a.d_in[pix];
+        const int pix = i * L + j;
+        const float2 vv = vst[pix], dd = d_in[pix];
         wreg[k] = make_float2(vv.x - dd.x, vv.y - dd.y);
         if (l >= 1) {
-          ynew[k] = a.yt[pix];
-          a.d_out[pix] = dd;
+          ynew[k] = yt[pix];
+          d_out[pix] = dd;
         }
       }
     }
   }
 
   if (a.check) {
-    __shared__ double red[3 * (kNT / 64)];
+    __shared__ double red[3 * (kNTR / 64)];
     double rdd = rd, rvd = rv, rzd = rz;
     block_sum3(rdd, rvd, rzd, red);
     if (threadIdx.x == 0) {
@@ -244,7 +369,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       buf[l * LS + lpad(j)] = wreg[k];
@@ -253,7 +378,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       if (l >= 1) {
@@ -267,35 +392,21 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNT;
+    const int p = threadIdx.x + k * kNTR;
     if (p < npx) {
       const int l = p / L, j = p - l * L;
       if (l >= 1) buf[l * LS + lpad(j)] = wreg[k];
     }
   }
   __syncthreads();
-  fft_lines<L, false, kNT, RT>(buf + LS, nr, tw);
-
-  // split C = F(ytilde) + i F(mu g) into the two half spectra and store
-  float4* __restrict__ sout = a.spec_out + mt.sp;
-  const int tot2 = nb * nr * C;
-  for (int q = threadIdx.x; q < tot2; q += kNT) {
-    const int c = q & (C - 1);
-    const int t2 = q >> logC;
-    const int l = t2 % nr, blk = t2 / nr;
-    const int kx = blk * C + c;
-    if (kx >= nh) continue;
-    const float2 cf = buf[(l + 1) * LS + lpad(kx)];
-    const float2 cm = buf[(l + 1) * LS + lpad(kx == 0 ? 0 : L - kx)];
-    sout[((long long)blk * M + r0 + l) * C + c] =
-        make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
-  }
+  fft_lines<L, false, kNTR, RT>(buf + LS, nr, tw);
+  split_store<L, RT>(a.spec_out + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
 }
 
 template <int L>
-__global__ void __launch_bounds__(kNT) row_kernel(RowArgs a) {
+__global__ void __launch_bounds__(kNTR) row_kernel(RowArgs a) {
   extern __shared__ float2 lds[];
-  const int4 t = a.tiles[blockIdx.x];
+  const int4 t = a.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (a.done && a.done[t.x]) return;
   row_tile<L>(a, t.x, t.y, lds);
 }
@@ -307,57 +418,82 @@ template <int L>
 __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, float2* lds) {
   constexpr int C = c_for(L);
   constexpr int LS = lstride(L);
+  constexpr int NQ = (L * C + kNTC - 1) / kNTC;
   const ImgMeta mt = a.meta[img];
   float2* buf = lds;
-  float2* tw = lds + 2 * C * LS;
-  load_twiddles<L, kNT>(tw, a.tw + mt.twc);
+  const float2* tw = twiddle_table<L, kNTC>(lds + 2 * C * LS, a.tw + mt.twc);
   const long long base = mt.sp + (long long)blk * L * C;
   const float4* __restrict__ sin = a.spec_in + base;
-  for (int q = threadIdx.x; q < L * C; q += kNT) {
-    const int i = q / C, c = q - i * C;
-    const float4 v = sin[q];
-    buf[(2 * c) * LS + lpad(i)] = make_float2(v.x, v.y);
-    buf[(2 * c + 1) * LS + lpad(i)] = make_float2(v.z, v.w);
-  }
-  __syncthreads();
-  fft_lines<L, false, kNT, 2 * C>(buf, 2 * C, tw);
-
-  const float mu = a.mu[img];
-  const float scale = 1.0f / ((float)L * (float)mt.n);
   const float2* __restrict__ hh = a.hh + mt.hh + (long long)blk * L * C;
   const float* __restrict__ dv2 = a.tab + mt.tab;
   const float* __restrict__ dh2 = dv2 + L;
-  for (int q = threadIdx.x; q < L * C; q += kNT) {
-    const int ky = q / C, c = q - ky * C;
-    const int kx = blk * C + c;
-    const float2 Y = buf[(2 * c) * LS + lpad(ky)];
-    const float2 G = buf[(2 * c + 1) * LS + lpad(ky)];
-    float2 X = make_float2(0.f, 0.f), Q = X;
-    if (kx < mt.nh) {
-      const float2 Hk = hh[q];
-      const float den = Hk.x * Hk.x + Hk.y * Hk.y + mu * (dh2[kx] + dv2[ky]);
-      const float inv = scale / den;
-      // conj(H) Y + G
-      X = make_float2((Hk.x * Y.x + Hk.y * Y.y + G.x) * inv, (Hk.x * Y.y - Hk.y * Y.x + G.y) * inv);
-      Q = cmul(Hk, X);
-      if (a.spec_store) a.spec_store[base + q] = make_float4(Y.x, Y.y, X.x, X.y);
+  const float mu = a.mu[img];
+  // every load of the tile first: spectra, blur spectrum, |D|^2 terms
+  float4 g[NQ];
+  float2 Hk[NQ];
+  float dsum[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTC;
+    if (q < L * C) {
+      const int ky = q / C, c = q - ky * C;
+      g[k] = sin[q];
+      Hk[k] = hh[q];
+      dsum[k] = dh2[blk * C + c] + dv2[ky];
     }
-    buf[(2 * c) * LS + lpad(ky)] = X;
-    buf[(2 * c + 1) * LS + lpad(ky)] = Q;
+  }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTC;
+    if (q < L * C) {
+      const int i = q / C, c = q - i * C;
+      buf[(2 * c) * LS + lpad(i)] = make_float2(g[k].x, g[k].y);
+      buf[(2 * c + 1) * LS + lpad(i)] = make_float2(g[k].z, g[k].w);
+    }
   }
   __syncthreads();
-  fft_lines<L, true, kNT, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, false, kNTC, 2 * C>(buf, 2 * C, tw);
+
+  const float scale = 1.0f / ((float)L * (float)mt.n);
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTC;
+    if (q < L * C) {
+      const int ky = q / C, c = q - ky * C;
+      const int kx = blk * C + c;
+      const float2 Y = buf[(2 * c) * LS + lpad(ky)];
+      const float2 G = buf[(2 * c + 1) * LS + lpad(ky)];
+      float2 X = make_float2(0.f, 0.f), Q = X;
+      if (kx < mt.nh) {
+        const float2 H = Hk[k];
+        const float den = H.x * H.x + H.y * H.y + mu * dsum[k];
+        const float inv = scale * frcp(den);
+        // conj(H) Y + G
+        X = make_float2((H.x * Y.x + H.y * Y.y + G.x) * inv, (H.x * Y.y - H.y * Y.x + G.y) * inv);
+        Q = cmul(H, X);
+        if (a.spec_store) a.spec_store[base + q] = make_float4(Y.x, Y.y, X.x, X.y);
+      }
+      buf[(2 * c) * LS + lpad(ky)] = X;
+      buf[(2 * c + 1) * LS + lpad(ky)] = Q;
+    }
+  }
+  __syncthreads();
+  fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
   float4* __restrict__ sout = a.spec_out + base;
-  for (int q = threadIdx.x; q < L * C; q += kNT) {
-    const int i = q / C, c = q - i * C;
-    const float2 X = buf[(2 * c) * LS + lpad(i)];
-    const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-    sout[q] = make_float4(X.x, X.y, Q.x, Q.y);
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTC;
+    if (q < L * C) {
+      const int i = q / C, c = q - i * C;
+      const float2 X = buf[(2 * c) * LS + lpad(i)];
+      const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
+      sout[q] = make_float4(X.x, X.y, Q.x, Q.y);
+    }
   }
 }
 
 template <int L>
-__global__ void __launch_bounds__(kNT) col_kernel(ColArgs a) {
+__global__ void __launch_bounds__(kNTC) col_kernel(ColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (a.done && a.done[t.x]) return;
@@ -422,25 +558,18 @@ __global__ void __launch_bounds__(kNT) fft_cols_kernel(float2* data, int W, int 
 // setup and initialisation
 // ---------------------------------------------------------------------------
 
-// embed kernel b circularly centred at the origin into a complex m' x n' grid
-__global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ h,
-                                 const long long* hoff, float2* grid, const long long* goff) {
-  const int img = blockIdx.y;
+// scatter kernel b circularly centred at the origin into a zeroed complex
+// m' x n' grid (2b < min(m', n'), so the taps land on distinct positions)
+__global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ h, const long long* hoff,
+                                 float2* grid, const long long* goff) {
+  const int img = blockIdx.x;
   const ImgMeta mt = meta[img];
-  const long long n = (long long)mt.m * mt.n;
-  float2* g = grid + goff[img];
   const int K = 2 * mt.b + 1;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
-    // position (i, j) collects h[b+p][b+q] with p = i (mod m'), q = j (mod n')
-    float s = 0.f;
-    for (int pp = -mt.b; pp <= mt.b; ++pp) {
-      if (((pp % mt.m) + mt.m) % mt.m != i) continue;
-      for (int qq = -mt.b; qq <= mt.b; ++qq)
-        if (((qq % mt.n) + mt.n) % mt.n == j) s += h[hoff[img] + (long long)(mt.b + pp) * K + (mt.b + qq)];
-    }
-    g[p] = make_float2(s, 0.f);
+  float2* g = grid + goff[img];
+  for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
+    const int pp = t / K - mt.b, qq = t % K - mt.b;
+    const int i = pp < 0 ? pp + mt.m : pp, j = qq < 0 ? qq + mt.n : qq;
+    g[(long long)i * mt.n + j] = make_float2(h[hoff[img] + t], 0.f);
   }
 }
 
@@ -449,32 +578,31 @@ __global__ void pack_half_kernel(const ImgMeta* meta, const float2* __restrict__
                                  const long long* goff, float2* hh) {
   const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
-  const long long tot = (long long)mt.m * mt.nb * mt.C;
   const float2* g = grid + goff[img];
-  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < tot;
-       q += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(q % mt.C);
-    const long long t = q / mt.C;
-    const int ky = (int)(t % mt.m), blk = (int)(t / mt.m);
-    const int kx = blk * mt.C + c;
-    hh[mt.hh + q] = kx < mt.nh ? g[(long long)ky * mt.n + kx] : make_float2(0.f, 0.f);
-  }
+  const int ncol = mt.nb * mt.C;
+  for (int ky = blockIdx.x; ky < mt.m; ky += gridDim.x)
+    for (int kx = threadIdx.x; kx < ncol; kx += blockDim.x)
+      hh[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))] =
+          kx < mt.nh ? g[(long long)ky * mt.n + kx] : make_float2(0.f, 0.f);
 }
 
-// per image: mean of the observed pixels (FP64)
-__global__ void __launch_bounds__(kNT) observed_mean_kernel(const ImgMeta* meta, const float* __restrict__ y,
-                                                           const uint8_t* __restrict__ mask, double* mean) {
-  const int img = blockIdx.x;
+constexpr int kMeanBlocks = 64;
+
+// per image and block of rows: FP64 sum and count of the observed pixels
+__global__ void __launch_bounds__(kNT) observed_sum_kernel(const ImgMeta* meta, const float* __restrict__ y,
+                                                          const uint8_t* __restrict__ mask, double* part) {
+  const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
   double s = 0.0, c = 0.0, dummy = 0.0;
-  const long long n = (long long)mt.m * mt.n;
-  for (long long p = threadIdx.x; p < n; p += kNT) {
-    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
-    if (observed(mt, mask, i, j)) { s += y[mt.px + p]; c += 1.0; }
-  }
+  for (int i = blockIdx.x; i < mt.m; i += gridDim.x)
+    for (int j = threadIdx.x; j < mt.n; j += kNT)
+      if (observed(mt, mask, i, j)) { s += y[mt.px + (long long)i * mt.n + j]; c += 1.0; }
   __shared__ double red[3 * (kNT / 64)];
   block_sum3(s, c, dummy, red);
-  if (threadIdx.x == 0) mean[img] = c > 0 ? s / c : 0.0;
+  if (threadIdx.x == 0) {
+    part[2 * ((long long)img * gridDim.x + blockIdx.x)] = s;
+    part[2 * ((long long)img * gridDim.x + blockIdx.x) + 1] = c;
+  }
 }
 
 __device__ __forceinline__ float init_value(const ImgMeta& mt, const float* __restrict__ y,
@@ -486,23 +614,34 @@ __device__ __forceinline__ float init_value(const ImgMeta& mt, const float* __re
   return observed(mt, mask, si, sj) ? y[mt.px + (long long)si * mt.n + sj] : mean;
 }
 
-// ytilde^0, v^0 = D ytilde^0, d^0 = 0
-__global__ void init_state_kernel(const ImgMeta* meta, const float* __restrict__ y,
-                                  const uint8_t* __restrict__ mask, const double* mean, float* yt,
-                                  float2* v, float2* d) {
+// ytilde^0, v^0 = D ytilde^0, d^0 = 0 (blocks of rows; mean from the partials)
+__global__ void __launch_bounds__(kNT) init_state_kernel(const ImgMeta* meta, const float* __restrict__ y,
+                                                        const uint8_t* __restrict__ mask, const double* part,
+                                                        int nparts, float* yt, float2* v, float2* d) {
   const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
-  const long long n = (long long)mt.m * mt.n;
-  const float mn = (float)mean[img];
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
-    const float c = init_value(mt, y, mask, mn, i, j);
-    const float r = init_value(mt, y, mask, mn, i, j + 1 == mt.n ? 0 : j + 1);
-    const float dn = init_value(mt, y, mask, mn, i + 1 == mt.m ? 0 : i + 1, j);
-    yt[mt.px + p] = c;
-    v[mt.px + p] = make_float2(r - c, dn - c);
-    d[mt.px + p] = make_float2(0.f, 0.f);
+  __shared__ float smean;
+  if (threadIdx.x == 0) {
+    double s = 0.0, c = 0.0;
+    for (int k = 0; k < nparts; ++k) {
+      s += part[2 * ((long long)img * nparts + k)];
+      c += part[2 * ((long long)img * nparts + k) + 1];
+    }
+    smean = c > 0 ? (float)(s / c) : 0.f;
+  }
+  __syncthreads();
+  const float mn = smean;
+  for (int i = blockIdx.x; i < mt.m; i += gridDim.x) {
+    const int id = i + 1 == mt.m ? 0 : i + 1;
+    for (int j = threadIdx.x; j < mt.n; j += kNT) {
+      const long long p = mt.px + (long long)i * mt.n + j;
+      const float c = init_value(mt, y, mask, mn, i, j);
+      const float r = init_value(mt, y, mask, mn, i, j + 1 == mt.n ? 0 : j + 1);
+      const float dn = init_value(mt, y, mask, mn, id, j);
+      yt[p] = c;
+      v[p] = make_float2(r - c, dn - c);
+      d[p] = make_float2(0.f, 0.f);
+    }
   }
 }
 
