@@ -150,8 +150,10 @@ deconv_status deconv_admm_run(deconv_plan p, const float* y, const uint8_t* mask
                               const float* lambda, const float* mu, int32_t iters, float* x_out,
                               float* ytilde_out, deconv_stats* stats);
 
-/* `iters` more iterations from the plan's current state (same lambda / mu
-   pointers as the run; read again).  Outputs as deconv_admm_run. */
+/* `iters` more iterations from the plan's current state (lambda / mu are read
+   again).  Outputs as deconv_admm_run.  Plans with explicit masks reuse the mask
+   pointer of the last deconv_admm_run, which must still be valid
+   (DECONV_ERR_STATE if there was no run). */
 deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const float* mu,
                                    int32_t iters, float* x_out, float* ytilde_out,
                                    deconv_stats* stats);
@@ -159,7 +161,8 @@ deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const flo
 /* Copy the resumable state w = [z; v; d] (Appendix B) out of / into the plan.
    ytilde: packed float (observed pixels hold y); v, d: packed float2 per
    pixel (horizontal, vertical).  Import also needs h for the spectrum (device
-   float, packed) and makes deconv_admm_continue start from this state. */
+   float, packed) and makes deconv_admm_continue start from this state; plans
+   with explicit masks need a previous deconv_admm_run (its mask is reused). */
 deconv_status deconv_state_export(deconv_plan p, float* ytilde, float* v, float* d);
 deconv_status deconv_state_import(deconv_plan p, const float* h, const float* mu,
                                   const float* ytilde, const float* v, const float* d);

@@ -2,7 +2,8 @@
 
     python -m paper_1602_01410_amd.build
 
-Compiles csrc/deconv.hip (which includes the kernel headers) with hipcc into
+Compiles the csrc/*.hip translation units (host code and the instantiations
+of each pass) with hipcc, in parallel, and links
 paper_1602_01410_amd/libdeconv.so.  Packed-FP32 instructions are disabled for
 all device code.
 """
@@ -30,13 +31,32 @@ def sources():
             if f.endswith((".hip", ".hpp", ".inc"))] + [os.path.join(ROOT, "include", "deconv.h")]
 
 
+def _units():
+    return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
 def build(verbose=False, jobs=None):
-    """Compile libdeconv.so.  Always recompiles (the caller decides when)."""
+    """Compile libdeconv.so: every csrc/*.hip translation unit in parallel,
+    then link.  Always recompiles (the caller decides when)."""
+    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-result", "-I" + os.path.join(ROOT, "include")]
+    tmpdir = os.path.join(HERE, "_build")
+    os.makedirs(tmpdir, exist_ok=True)
+    procs = []
+    objs = []
+    for u in _units():
+        obj = os.path.join(tmpdir, u.replace(".hip", ".o"))
+        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, u), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((u, subprocess.Popen(cmd)))
+        objs.append(obj)
+    failed = [u for u, pr in procs if pr.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed for " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-result", "-I" + os.path.join(ROOT, "include"),
-           os.path.join(CSRC, "deconv.hip"), "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

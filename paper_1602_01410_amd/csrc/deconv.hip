@@ -1,5 +1,6 @@
 // Host side of the partial-ADMM library: plans, workspace layout, launch
 // schedule and the C ABI declared in include/deconv.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,29 +9,17 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <new>
 #include <vector>
 #include <cstdint>
 
 #include "../../include/deconv.h"
-#include "kernels.hpp"
-#include "backward.hpp"
+#include "launch.hpp"
+#include "setup.hpp"
+#include "backward_setup.hpp"
 
 using namespace dcv;
-
-// every supported line length: 2^a 3^c, a >= 1, c <= 2, 8 <= L <= 2048
-#define DCV_FOR_EACH_LEN(X)                                                                    \
-  X(8) X(12) X(16) X(18) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(128) X(144) X(192)   \
-  X(256) X(288) X(384) X(512) X(576) X(768) X(1024) X(1152) X(1536) X(2048)
-
-static bool supported_len(int L) {
-  switch (L) {
-#define DCV_CASE(n) case n: return true;
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return false;
-}
 
 #define HIPCHK(expr)                                                      \
   do {                                                                    \
@@ -48,69 +37,6 @@ static bool supported_len(int L) {
     if (s_ != DECONV_OK) return s_;                \
   } while (0)
 
-// ---------------------------------------------------------------------------
-// kernel dispatch by compile-time length
-// ---------------------------------------------------------------------------
-static size_t row_lds_bytes(int L) {
-  size_t e = 0;
-  switch (L) {
-#define DCV_CASE(n) case n: e = row_lds_elems(n); break;
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return e * sizeof(float2);
-}
-static size_t col_lds_bytes(int L) {
-  size_t e = 0;
-  switch (L) {
-#define DCV_CASE(n) case n: e = col_lds_elems(n); break;
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return e * sizeof(float2);
-}
-
-template <typename K>
-static hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void** args, int nt = kNT) {
-  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(nt), args, lds, s);
-}
-
-static hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a) {
-  void* args[] = {&a};
-  switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(row_kernel<n>, grid, lds, s, args, kNTR);
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return hipErrorInvalidValue;
-}
-static hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a) {
-  void* args[] = {&a};
-  switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(col_kernel<n>, grid, lds, s, args, kNTC);
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return hipErrorInvalidValue;
-}
-static hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a) {
-  void* args[] = {&a};
-  switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(bwd_row_kernel<n>, grid, lds, s, args, kNTR);
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return hipErrorInvalidValue;
-}
-static hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a) {
-  void* args[] = {&a};
-  switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(bwd_col_kernel<n>, grid, lds, s, args, kNTC);
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return hipErrorInvalidValue;
-}
 static size_t fftrow_lds_bytes(int L) {
   int lpw = std::max(1, std::min(32, 4096 / L));
   return (size_t)(lpw * lstride(L) + L) * sizeof(float2);
@@ -123,7 +49,7 @@ static hipError_t launch_fft_rows(int L, float2* data, long long nrows, const fl
   int grid = (int)((nrows + lpw - 1) / lpw);
   void* args[] = {&data, &nrows, &tw, &inverse};
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(fft_rows_kernel<n>, grid, fftrow_lds_bytes(n), s, args);
+#define DCV_CASE(n) case n: return launch_lds(fft_rows_kernel<n>, grid, fftrow_lds_bytes(n), s, args, kNT);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
@@ -135,7 +61,7 @@ static hipError_t launch_fft_cols(int L, float2* data, int W, int count, const f
   int grid = count * ((W + cw - 1) / cw);
   void* args[] = {&data, &W, &count, &tw, &inverse};
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(fft_cols_kernel<n>, grid, fftcol_lds_bytes(n), s, args);
+#define DCV_CASE(n) case n: return launch_lds(fft_cols_kernel<n>, grid, fftcol_lds_bytes(n), s, args, kNT);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
@@ -186,12 +112,67 @@ static const float2* cached_twiddles(int L) {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+// one launch of a pass: line length L (0 = several lengths, dispatched per
+// tile) over tiles [tile0, tile0 + ntiles) of the tile table
 struct Group {
   int L;
-  long long tile0;  // first tile in the tile table
+  long long tile0;
   int ntiles;
   size_t lds;
 };
+
+// A tile of a pass: image, first row (row pass) or column block (column
+// pass), and its relative cost.
+struct TileRef {
+  int img, pos;
+  double cost;
+};
+
+// Dispatch order of one launch.  Workgroups go round-robin to the 8 XCDs
+// (block b to XCD b mod 8), each with its own L2.  Every XCD gets contiguous
+// runs of an image's tiles (neighbouring row tiles share halo rows, which then
+// meet in one L2); images with many tiles are split into 8 runs; runs are
+// given to the least-loaded XCD, largest first; within an XCD the costliest
+// tiles come first.  Slots left over are padding (image -1).
+static void xcd_schedule(const std::vector<std::vector<TileRef>>& images, std::vector<int4>& out) {
+  constexpr int kXcd = 8;
+  struct Run { int img; size_t a, b; double cost, tile_cost; };
+  std::vector<Run> runs;
+  for (size_t i = 0; i < images.size(); ++i) {
+    const auto& t = images[i];
+    if (t.empty()) continue;
+    const size_t n = t.size();
+    const size_t parts = n >= 2 * kXcd ? kXcd : 1;
+    for (size_t k = 0; k < parts; ++k) {
+      size_t a = n * k / parts, b = n * (k + 1) / parts;
+      double c = 0;
+      for (size_t q = a; q < b; ++q) c += t[q].cost;
+      runs.push_back(Run{(int)i, a, b, c, t[a].cost});
+    }
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) { return x.cost > y.cost; });
+  std::vector<double> load(kXcd, 0.0);
+  std::vector<std::vector<Run>> per(kXcd);
+  for (const Run& r : runs) {
+    int best = 0;
+    for (int x = 1; x < kXcd; ++x)
+      if (load[x] < load[best]) best = x;
+    load[best] += r.cost;
+    per[best].push_back(r);
+  }
+  size_t maxlen = 0;
+  std::vector<std::vector<int4>> lists(kXcd);
+  for (int x = 0; x < kXcd; ++x) {
+    std::stable_sort(per[x].begin(), per[x].end(),
+                     [](const Run& u, const Run& w) { return u.tile_cost > w.tile_cost; });
+    for (const Run& r : per[x])
+      for (size_t q = r.a; q < r.b; ++q) lists[x].push_back(make_int4(r.img, images[r.img][q].pos, 0, 0));
+    maxlen = std::max(maxlen, lists[x].size());
+  }
+  for (size_t k = 0; k < maxlen; ++k)
+    for (int x = 0; x < kXcd; ++x)
+      out.push_back(k < lists[x].size() ? lists[x][k] : make_int4(-1, 0, 0, 0));
+}
 
 struct deconv_plan_s {
   int batch = 0;
@@ -248,8 +229,10 @@ struct deconv_plan_s {
   std::vector<long long> hoff_h;
   std::map<int, long long> tw_off;
   std::vector<Group> row_groups, col_groups;
+  std::vector<int4> h_tiles;  // all tile tables, uploaded at plan creation
   std::vector<std::vector<Group>> row_img, col_img;  // per-image launches (batched = 0)
 
+  const uint8_t* mask = nullptr;  // explicit masks of the last run (caller-owned)
   int cur_d = 0;        // index of the d buffer holding the current state
   bool have_state = false;
   int last_iters = 0;   // iterations of the last run (for the backward)
@@ -332,30 +315,43 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   p->total_px = px; p->total_sp = sp; p->total_hh = hhp; p->total_tab = tab; p->total_tw = tw;
   p->total_rt = rt; p->total_h = hk; p->tw_off = twoff;
 
-  // tiles: grouped by length, images contiguous inside a group
-  long long ntiles = 0;
+  // tile tables: one XCD-interleaved schedule per pass for the batched launch
+  // and one per image for the per-image launches (batched = 0)
+  p->h_tiles.clear();
   p->row_groups.clear(); p->col_groups.clear();
   p->row_img.assign(B, {}); p->col_img.assign(B, {});
-  std::map<int, std::vector<int>> by_w, by_h;
-  for (int b = 0; b < B; ++b) { by_w[p->desc[b].width].push_back(b); by_h[p->desc[b].height].push_back(b); }
-  for (auto& kv : by_w) {
-    Group g{kv.first, ntiles, 0, row_lds_bytes(kv.first)};
-    for (int b : kv.second) {
-      p->row_img[b].push_back(Group{kv.first, ntiles, p->meta[b].nrt, g.lds});
-      g.ntiles += p->meta[b].nrt;
-      ntiles += p->meta[b].nrt;
+  std::vector<std::vector<TileRef>> rt_tiles(B), ct_tiles(B);
+  std::set<int> widths, heights;
+  for (int b = 0; b < B; ++b) {
+    const ImgMeta& m = p->meta[b];
+    widths.insert(m.n);
+    heights.insert(m.m);
+    const double lr = std::log2((double)m.n), lc = std::log2((double)m.m);
+    for (int t = 0; t < m.nrt; ++t) {
+      const int nr = std::min(m.rt, m.m - t * m.rt);
+      rt_tiles[b].push_back(TileRef{b, t * m.rt, (double)(nr + 2) * m.n * lr});
     }
-    p->row_groups.push_back(g);
+    for (int t = 0; t < m.nb; ++t) ct_tiles[b].push_back(TileRef{b, t, (double)m.C * m.m * lc});
   }
-  for (auto& kv : by_h) {
-    Group g{kv.first, ntiles, 0, col_lds_bytes(kv.first)};
-    for (int b : kv.second) {
-      p->col_img[b].push_back(Group{kv.first, ntiles, p->meta[b].nb, g.lds});
-      g.ntiles += p->meta[b].nb;
-      ntiles += p->meta[b].nb;
-    }
-    p->col_groups.push_back(g);
+  size_t rlds = 0, clds = 0;
+  for (int w : widths) rlds = std::max(rlds, row_lds_bytes(w));
+  for (int h : heights) clds = std::max(clds, col_lds_bytes(h));
+  auto add_group = [&](std::vector<Group>& dst, int L, size_t lds, const std::vector<std::vector<TileRef>>& imgs) {
+    const long long t0 = (long long)p->h_tiles.size();
+    xcd_schedule(imgs, p->h_tiles);
+    dst.push_back(Group{L, t0, (int)((long long)p->h_tiles.size() - t0), lds});
+  };
+  add_group(p->row_groups, widths.size() == 1 ? *widths.begin() : 0, rlds, rt_tiles);
+  add_group(p->col_groups, heights.size() == 1 ? *heights.begin() : 0, clds, ct_tiles);
+  for (int b = 0; b < B; ++b) {
+    std::vector<std::vector<TileRef>> one(B);
+    one[b] = rt_tiles[b];
+    add_group(p->row_img[b], p->meta[b].n, row_lds_bytes(p->meta[b].n), one);
+    one[b].clear();
+    one[b] = ct_tiles[b];
+    add_group(p->col_img[b], p->meta[b].m, col_lds_bytes(p->meta[b].m), one);
   }
+  const long long ntiles = (long long)p->h_tiles.size();
 
   const size_t A = 256;
   size_t o = 0;
@@ -514,15 +510,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   }
 
   // host-built tables
-  std::vector<int4> tiles;
-  for (auto& g : p->row_groups)
-    for (int b = 0; b < batch; ++b)
-      if (p->desc[b].width == g.L)
-        for (int t = 0; t < p->meta[b].nrt; ++t) tiles.push_back(make_int4(b, t * p->meta[b].rt, 0, 0));
-  for (auto& g : p->col_groups)
-    for (int b = 0; b < batch; ++b)
-      if (p->desc[b].height == g.L)
-        for (int t = 0; t < p->meta[b].nb; ++t) tiles.push_back(make_int4(b, t, 0, 0));
+  const std::vector<int4>& tiles = p->h_tiles;
   std::vector<float2> tw(p->total_tw);
   for (auto& kv : p->tw_off) {
     std::vector<float2> t;
@@ -637,56 +625,53 @@ static hipEvent_t take_event(deconv_plan_s* p) {
   return e;
 }
 
-// bracket a pass with events when profiling (never inside a capture)
+// With opt.profile (and outside a graph capture) a pass gets a start event on
+// its first launch and a stop event on its last one.
 struct PassTimer {
   deconv_plan_s* p;
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* dst;
-  hipEvent_t a = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
   PassTimer(deconv_plan_s* p_, std::vector<std::pair<hipEvent_t, hipEvent_t>>* d) : p(p_), dst(d) {
     if (p->opt.profile && p->ls == p->stream) {
       a = take_event(p);
-      if (a) (void)hipEventRecord(a, p->ls);
+      b = take_event(p);
+      if (!a || !b) a = b = nullptr;
     }
   }
-  ~PassTimer() {
-    if (!a) return;
-    hipEvent_t b = take_event(p);
-    if (b && hipEventRecord(b, p->ls) == hipSuccess) dst->emplace_back(a, b);
-  }
+  hipEvent_t start(size_t idx) const { return idx == 0 ? a : nullptr; }
+  hipEvent_t stop(size_t idx, size_t n) const { return idx + 1 == n ? b : nullptr; }
+  void done() { if (a) dst->emplace_back(a, b); }
 };
+
+// the groups one pass launches: one per line length (batched) or per image
+static const std::vector<Group> pass_groups(deconv_plan_s* p, bool rows) {
+  if (p->opt.batched) return rows ? p->row_groups : p->col_groups;
+  std::vector<Group> g;
+  for (int b = 0; b < p->batch; ++b)
+    for (auto& x : (rows ? p->row_img[b] : p->col_img[b])) g.push_back(x);
+  return g;
+}
 
 // launch the row pass over every image (batched) or image by image
 static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
   PassTimer timer(p, &p->ev_row);
-  if (p->opt.batched) {
-    for (auto& g : p->row_groups) {
-      a.tiles = p->d_tiles + g.tile0;
-      HIPCHK(launch_row(g.L, g.ntiles, g.lds, p->ls, a));
-    }
-  } else {
-    for (int b = 0; b < p->batch; ++b)
-      for (auto& g : p->row_img[b]) {
-        a.tiles = p->d_tiles + g.tile0;
-        HIPCHK(launch_row(g.L, g.ntiles, g.lds, p->ls, a));
-      }
+  const std::vector<Group>& gs = p->opt.batched ? p->row_groups : pass_groups(p, true);
+  for (size_t k = 0; k < gs.size(); ++k) {
+    a.tiles = p->d_tiles + gs[k].tile0;
+    HIPCHK(launch_row(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size())));
   }
+  timer.done();
   return DECONV_OK;
 }
 
 static deconv_status launch_cols(deconv_plan_s* p, ColArgs a) {
   PassTimer timer(p, &p->ev_col);
-  if (p->opt.batched) {
-    for (auto& g : p->col_groups) {
-      a.tiles = p->d_tiles + g.tile0;
-      HIPCHK(launch_col(g.L, g.ntiles, g.lds, p->ls, a));
-    }
-  } else {
-    for (int b = 0; b < p->batch; ++b)
-      for (auto& g : p->col_img[b]) {
-        a.tiles = p->d_tiles + g.tile0;
-        HIPCHK(launch_col(g.L, g.ntiles, g.lds, p->ls, a));
-      }
+  const std::vector<Group>& gs = p->opt.batched ? p->col_groups : pass_groups(p, false);
+  for (size_t k = 0; k < gs.size(); ++k) {
+    a.tiles = p->d_tiles + gs[k].tile0;
+    HIPCHK(launch_col(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size())));
   }
+  timer.done();
   return DECONV_OK;
 }
 
@@ -884,6 +869,7 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   hipStream_t s = p->stream;
   p->have_state = false;
   p->ck_valid = false;
+  p->mask = mask;
   STCHK(setup_spectrum(p, h, nullptr));
   STCHK(reset_counters(p));
   hipLaunchKernelGGL(observed_sum_kernel, dim3(kMeanBlocks, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask,
@@ -905,12 +891,11 @@ extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda
                                               float* x_out, float* ytilde_out, deconv_stats* stats) {
   if (!p || !lambda || !mu || !x_out || iters < 1) return DECONV_ERR_INVALID_ARG;
   if (!p->have_state) return DECONV_ERR_STATE;
-  // the mask pointer is not retained: continuing requires implicit masks
-  if (needs_mask(p)) return DECONV_ERR_INVALID_ARG;
+  if (needs_mask(p) && !p->mask) return DECONV_ERR_STATE;
   p->ck_valid = false;
   STCHK(reset_counters(p));
   STCHK(prologue_from_state(p, mu));
-  STCHK(iterate(p, nullptr, lambda, mu, iters, x_out, false));
+  STCHK(iterate(p, p->mask, lambda, mu, iters, x_out, false));
   return finish(p, iters, ytilde_out, stats);
 }
 
@@ -928,7 +913,7 @@ extern "C" deconv_status deconv_state_export(deconv_plan p, float* ytilde, float
 extern "C" deconv_status deconv_state_import(deconv_plan p, const float* h, const float* mu, const float* ytilde,
                                              const float* v, const float* d) {
   if (!p || !h || !mu || !ytilde || !v || !d) return DECONV_ERR_INVALID_ARG;
-  if (needs_mask(p)) return DECONV_ERR_INVALID_ARG;
+  if (needs_mask(p) && !p->mask) return DECONV_ERR_STATE;
   hipStream_t s = p->stream;
   const size_t n = (size_t)p->total_px;
   STCHK(setup_spectrum(p, h, nullptr));

@@ -150,17 +150,6 @@ __device__ __forceinline__ bool observed(const ImgMeta& mt, const uint8_t* __res
 
 __device__ __forceinline__ int wrapi(int i, int M) { return i < 0 ? i + M : (i >= M ? i - M : i); }
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Remap the block index so that each XCD gets a contiguous range of
-// tiles: neighbouring row tiles (which share halo rows) then meet in the
-// same L2.  A bijection on [0, nblocks).
-__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
-  constexpr int kXcd = 8;
-  const int q = nblocks / kXcd, r = nblocks % kXcd;
-  const int x = b % kXcd, k = b / kXcd;
-  return x * q + (x < r ? x : r) + k;
-}
-
 // reciprocal with one Newton step (error below 1 ulp of the exact division)
 __device__ __forceinline__ float frcp(float x) {
   float r = __builtin_amdgcn_rcpf(x);
@@ -403,12 +392,32 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   split_store<L, RT>(a.spec_out + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
 }
 
+// Tile tables are built on the host in dispatch order (XCD-interleaved, see
+// deconv.hip); entries with image -1 are padding.
 template <int L>
 __global__ void __launch_bounds__(kNTR) row_kernel(RowArgs a) {
   extern __shared__ float2 lds[];
-  const int4 t = a.tiles[xcd_remap(blockIdx.x, gridDim.x)];
-  if (a.done && a.done[t.x]) return;
+  const int4 t = a.tiles[blockIdx.x];
+  if (t.x < 0 || (a.done && a.done[t.x])) return;
   row_tile<L>(a, t.x, t.y, lds);
+}
+
+// one launch for tiles of every line length: dispatch on the tile's length
+template <int L0, int... Ls>
+__device__ __forceinline__ void row_dispatch(const RowArgs& a, int L, int img, int r0, float2* lds) {
+  if (L == L0) {
+    row_tile<L0>(a, img, r0, lds);
+    return;
+  }
+  if constexpr (sizeof...(Ls) > 0) row_dispatch<Ls...>(a, L, img, r0, lds);
+}
+
+template <int... Ls>
+__global__ void __launch_bounds__(kNTR) row_kernel_multi(RowArgs a) {
+  extern __shared__ float2 lds[];
+  const int4 t = a.tiles[blockIdx.x];
+  if (t.x < 0 || (a.done && a.done[t.x])) return;
+  row_dispatch<Ls...>(a, a.meta[t.x].n, t.x, t.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -496,178 +505,25 @@ template <int L>
 __global__ void __launch_bounds__(kNTC) col_kernel(ColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
-  if (a.done && a.done[t.x]) return;
+  if (t.x < 0 || (a.done && a.done[t.x])) return;
   col_tile<L>(a, t.x, t.y, lds);
 }
 
-// ---------------------------------------------------------------------------
-// plain batched 2-D FFT passes (setup of the blur spectrum, diagnostics)
-// data: float2 [count][H][W] row-major
-// ---------------------------------------------------------------------------
-template <int L>  // L = W
-__global__ void __launch_bounds__(kNT) fft_rows_kernel(float2* data, long long nrows_total,
-                                                       const float2* tw_glob, int inverse) {
+template <int L0, int... Ls>
+__device__ __forceinline__ void col_dispatch(const ColArgs& a, int L, int img, int blk, float2* lds) {
+  if (L == L0) {
+    col_tile<L0>(a, img, blk, lds);
+    return;
+  }
+  if constexpr (sizeof...(Ls) > 0) col_dispatch<Ls...>(a, L, img, blk, lds);
+}
+
+template <int... Ls>
+__global__ void __launch_bounds__(kNTC) col_kernel_multi(ColArgs a) {
   extern __shared__ float2 lds[];
-  constexpr int LPW = 4096 / L < 1 ? 1 : (4096 / L > 32 ? 32 : 4096 / L);
-  constexpr int LS = lstride(L);
-  float2* tw = lds + LPW * LS;
-  load_twiddles<L, kNT>(tw, tw_glob);
-  const long long row0 = (long long)blockIdx.x * LPW;
-  const int nl = (int)min((long long)LPW, nrows_total - row0);
-  for (int q = threadIdx.x; q < nl * L; q += kNT) {
-    const int l = q / L, j = q - l * L;
-    lds[l * LS + lpad(j)] = data[(row0 + l) * L + j];
-  }
-  __syncthreads();
-  if (inverse) fft_lines<L, true, kNT, LPW>(lds, nl, tw);
-  else fft_lines<L, false, kNT, LPW>(lds, nl, tw);
-  for (int q = threadIdx.x; q < nl * L; q += kNT) {
-    const int l = q / L, j = q - l * L;
-    data[(row0 + l) * L + j] = lds[l * LS + lpad(j)];
-  }
-}
-
-template <int L>  // L = H
-__global__ void __launch_bounds__(kNT) fft_cols_kernel(float2* data, int W, int count,
-                                                       const float2* tw_glob, int inverse) {
-  extern __shared__ float2 lds[];
-  constexpr int CW = c_for(L) * 2;   // columns per workgroup
-  constexpr int LS = lstride(L);
-  float2* tw = lds + CW * LS;
-  load_twiddles<L, kNT>(tw, tw_glob);
-  const int nblk = (W + CW - 1) / CW;
-  const int img = blockIdx.x / nblk, blk = blockIdx.x - img * nblk;
-  if (img >= count) return;
-  float2* base = data + (long long)img * L * W;
-  const int c0 = blk * CW;
-  const int nc = min(CW, W - c0);
-  for (int q = threadIdx.x; q < L * CW; q += kNT) {
-    const int i = q / CW, c = q - i * CW;
-    if (c < nc) lds[c * LS + lpad(i)] = base[(long long)i * W + c0 + c];
-  }
-  __syncthreads();
-  if (inverse) fft_lines<L, true, kNT, CW>(lds, nc, tw);
-  else fft_lines<L, false, kNT, CW>(lds, nc, tw);
-  for (int q = threadIdx.x; q < L * CW; q += kNT) {
-    const int i = q / CW, c = q - i * CW;
-    if (c < nc) base[(long long)i * W + c0 + c] = lds[c * LS + lpad(i)];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// setup and initialisation
-// ---------------------------------------------------------------------------
-
-// scatter kernel b circularly centred at the origin into a zeroed complex
-// m' x n' grid (2b < min(m', n'), so the taps land on distinct positions)
-__global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ h, const long long* hoff,
-                                 float2* grid, const long long* goff) {
-  const int img = blockIdx.x;
-  const ImgMeta mt = meta[img];
-  const int K = 2 * mt.b + 1;
-  float2* g = grid + goff[img];
-  for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
-    const int pp = t / K - mt.b, qq = t % K - mt.b;
-    const int i = pp < 0 ? pp + mt.m : pp, j = qq < 0 ? qq + mt.n : qq;
-    g[(long long)i * mt.n + j] = make_float2(h[hoff[img] + t], 0.f);
-  }
-}
-
-// copy the spectrum columns kx < nh into the tiled half layout
-__global__ void pack_half_kernel(const ImgMeta* meta, const float2* __restrict__ grid,
-                                 const long long* goff, float2* hh) {
-  const int img = blockIdx.y;
-  const ImgMeta mt = meta[img];
-  const float2* g = grid + goff[img];
-  const int ncol = mt.nb * mt.C;
-  for (int ky = blockIdx.x; ky < mt.m; ky += gridDim.x)
-    for (int kx = threadIdx.x; kx < ncol; kx += blockDim.x)
-      hh[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))] =
-          kx < mt.nh ? g[(long long)ky * mt.n + kx] : make_float2(0.f, 0.f);
-}
-
-constexpr int kMeanBlocks = 64;
-
-// per image and block of rows: FP64 sum and count of the observed pixels
-__global__ void __launch_bounds__(kNT) observed_sum_kernel(const ImgMeta* meta, const float* __restrict__ y,
-                                                          const uint8_t* __restrict__ mask, double* part) {
-  const int img = blockIdx.y;
-  const ImgMeta mt = meta[img];
-  double s = 0.0, c = 0.0, dummy = 0.0;
-  for (int i = blockIdx.x; i < mt.m; i += gridDim.x)
-    for (int j = threadIdx.x; j < mt.n; j += kNT)
-      if (observed(mt, mask, i, j)) { s += y[mt.px + (long long)i * mt.n + j]; c += 1.0; }
-  __shared__ double red[3 * (kNT / 64)];
-  block_sum3(s, c, dummy, red);
-  if (threadIdx.x == 0) {
-    part[2 * ((long long)img * gridDim.x + blockIdx.x)] = s;
-    part[2 * ((long long)img * gridDim.x + blockIdx.x) + 1] = c;
-  }
-}
-
-__device__ __forceinline__ float init_value(const ImgMeta& mt, const float* __restrict__ y,
-                                            const uint8_t* __restrict__ mask, float mean, int i, int j) {
-  if (observed(mt, mask, i, j)) return y[mt.px + (long long)i * mt.n + j];
-  const bool in_c = i >= mt.b && i < mt.m - mt.b && j >= mt.b && j < mt.n - mt.b;
-  if (in_c) return mean;
-  const int si = min(max(i, mt.b), mt.m - mt.b - 1), sj = min(max(j, mt.b), mt.n - mt.b - 1);
-  return observed(mt, mask, si, sj) ? y[mt.px + (long long)si * mt.n + sj] : mean;
-}
-
-// ytilde^0, v^0 = D ytilde^0, d^0 = 0 (blocks of rows; mean from the partials)
-__global__ void __launch_bounds__(kNT) init_state_kernel(const ImgMeta* meta, const float* __restrict__ y,
-                                                        const uint8_t* __restrict__ mask, const double* part,
-                                                        int nparts, float* yt, float2* v, float2* d) {
-  const int img = blockIdx.y;
-  const ImgMeta mt = meta[img];
-  __shared__ float smean;
-  if (threadIdx.x == 0) {
-    double s = 0.0, c = 0.0;
-    for (int k = 0; k < nparts; ++k) {
-      s += part[2 * ((long long)img * nparts + k)];
-      c += part[2 * ((long long)img * nparts + k) + 1];
-    }
-    smean = c > 0 ? (float)(s / c) : 0.f;
-  }
-  __syncthreads();
-  const float mn = smean;
-  for (int i = blockIdx.x; i < mt.m; i += gridDim.x) {
-    const int id = i + 1 == mt.m ? 0 : i + 1;
-    for (int j = threadIdx.x; j < mt.n; j += kNT) {
-      const long long p = mt.px + (long long)i * mt.n + j;
-      const float c = init_value(mt, y, mask, mn, i, j);
-      const float r = init_value(mt, y, mask, mn, i, j + 1 == mt.n ? 0 : j + 1);
-      const float dn = init_value(mt, y, mask, mn, id, j);
-      yt[p] = c;
-      v[p] = make_float2(r - c, dn - c);
-      d[p] = make_float2(0.f, 0.f);
-    }
-  }
-}
-
-// per image: FP64 sum of the row-tile partials -> |d'-d|, |v'-v|, |z'-z|;
-// optionally sets the stop flag
-__global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, const double* partials,
-                                                       double* res, int* done, int* nonfinite,
-                                                       int* iters_done, int iters_since,
-                                                       double tol_p, double tol_d) {
-  const int img = blockIdx.x;
-  const ImgMeta mt = meta[img];
-  double a = 0, b = 0, c = 0;
-  for (int t = threadIdx.x; t < mt.nrt; t += kNT) {
-    const double* p = partials + 3 * (mt.rt0 + t);
-    a += p[0]; b += p[1]; c += p[2];
-  }
-  __shared__ double red[3 * (kNT / 64)];
-  block_sum3(a, b, c, red);
-  if (threadIdx.x == 0) {
-    if (done && done[img]) return;
-    res[3 * img] = sqrt(a); res[3 * img + 1] = sqrt(b); res[3 * img + 2] = sqrt(c);
-    if (!isfinite(a) || !isfinite(b) || !isfinite(c)) nonfinite[img] = 1;
-    iters_done[img] += iters_since;
-    const double sc = sqrt(2.0 * (double)mt.m * (double)mt.n);
-    if (done && (tol_p > 0 || tol_d > 0) && sqrt(a) <= tol_p * sc && sqrt(b) <= tol_d * sc) done[img] = 1;
-  }
+  const int4 t = a.tiles[blockIdx.x];
+  if (t.x < 0 || (a.done && a.done[t.x])) return;
+  col_dispatch<Ls...>(a, a.meta[t.x].m, t.x, t.y, lds);
 }
 
 }  // namespace dcv

@@ -1,0 +1,26 @@
+// Instantiations and launcher of one pass (see launch.hpp).
+#include "launch.hpp"
+
+namespace dcv {
+
+size_t row_lds_bytes(int L) {
+  switch (L) {
+#define DCV_CASE(n) case n: return row_lds_elems(n) * sizeof(float2);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return 0;
+}
+
+hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0, hipEvent_t e1) {
+  void* args[] = {&a};
+  if (L == 0) return launch_lds(row_kernel_multi<DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(row_kernel<n>, grid, lds, s, args, kNTR, e0, e1);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dcv

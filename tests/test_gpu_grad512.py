@@ -1,0 +1,102 @@
+"""Gradients of the 16 x 512^2 workload (50 unrolled iterations, checkpoint
+every 10): the adjoint kernels against central finite differences of the
+HIP forward pass, and against the FP64 oracle adjoint on a sampled image."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_01410_amd import synth
+
+from .gpu_util import desc, device_inputs, explicit_mask, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    import torch
+    from paper_1602_01410_amd import binding
+    probs = synth.config_grad_512()
+    iters = probs[0]["iters"]
+    plan = binding.Plan([desc(p) for p in probs], ckpt_every=10, max_iters=iters)
+    y, mask, h, lam, mu = device_inputs(probs)
+    xt = torch.from_numpy(np.concatenate([p["x_true"].ravel() for p in probs])).cuda().double()
+    return probs, iters, plan, y, mask, h, lam, mu, xt
+
+
+def _loss(plan, y, mask, h, lam, mu, iters, xt):
+    """Mean squared error to the ground truth (float64 on the device)."""
+    x, _ = plan.run(y, mask, h, lam, mu, iters)
+    d = x.double() - xt
+    return float((d * d).sum() / d.numel()), x
+
+
+@pytest.mark.timeout(300)
+def test_grad512_finite_differences():
+    import torch
+    probs, iters, plan, y, mask, h, lam, mu, xt = _setup()
+    L0, x = _loss(plan, y, mask, h, lam, mu, iters, xt)
+    gx = (2.0 * (x.double() - xt) / x.numel()).float()
+    gy, gl, gh = plan.backward(y, mask, h, lam, mu, gx)
+    torch.cuda.synchronize()
+    obs = torch.from_numpy(np.concatenate([p["mask"].ravel() for p in probs]).astype(bool)).cuda()
+    rms_y = float(torch.sqrt((y[obs].double() ** 2).mean()))
+    hmax = float(h.abs().max())
+    eps = 1e-3
+
+    def fd_and_adjoint(dy, dl, dh):
+        ana = float((gy.double() * dy).sum() + (gl.double() * dl).sum() + (gh.double() * dh).sum())
+        Lp, _ = _loss(plan, (y.double() + eps * dy).float(), mask, (h.double() + eps * dh).float(),
+                      (lam.double() + eps * dl).float(), mu, iters, xt)
+        Lm, _ = _loss(plan, (y.double() - eps * dy).float(), mask, (h.double() - eps * dh).float(),
+                      (lam.double() - eps * dl).float(), mu, iters, xt)
+        return (Lp - Lm) / (2 * eps), ana
+
+    # 8 seeded random directions, each block scaled by its own magnitude
+    fds, anas = [], []
+    for k, seed in enumerate(range(500, 508)):
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        uy = torch.randn(y.numel(), generator=g, dtype=torch.float64).cuda() * obs
+        ul = torch.randn(lam.numel(), generator=g, dtype=torch.float64).cuda()
+        uh = torch.randn(h.numel(), generator=g, dtype=torch.float64).cuda()
+        fd, ana = fd_and_adjoint(uy * rms_y, ul * lam.double(), uh * hmax)
+        fds.append(fd)
+        anas.append(ana)
+        log("direction %d: fd %.6e adjoint %.6e rel %.2e" % (k, fd, ana, abs(fd - ana) / abs(fd)))
+    fds, anas = np.array(fds), np.array(anas)
+    agg = np.linalg.norm(fds - anas) / np.linalg.norm(anas)
+    log("random directions: aggregate relative difference %.2e" % agg)
+    # the gradient direction (same block scaling): largest directional
+    # derivative, so the FP32 rounding noise of the loss is negligible
+    sy, sl, sh = rms_y ** 2, lam.double() ** 2, hmax ** 2
+    dy, dl, dh = gy.double() * sy * obs, gl.double() * sl, gh.double() * sh
+    nrm = float(torch.sqrt((dy * dy / sy).sum() + (dl * dl / sl).sum() + (dh * dh / sh).sum()))
+    fd, ana = fd_and_adjoint(dy / nrm, dl / nrm, dh / nrm)
+    rel = abs(fd - ana) / abs(fd)
+    log("gradient direction: fd %.6e adjoint %.6e rel %.2e" % (fd, ana, rel))
+    # FP32 forward passes: the loss carries ~5e-9 of rounding noise, about 1%
+    # of the random-direction differences at eps = 1e-3
+    assert rel <= 1e-3, rel
+    assert agg <= 5e-2, agg
+    assert (np.sign(fds) == np.sign(anas)).all()
+
+
+@pytest.mark.timeout(300)
+def test_grad512_sampled_image_vs_oracle():
+    import torch
+    probs, iters, plan, y, mask, h, lam, mu, xt = _setup()
+    L0, x = _loss(plan, y, mask, h, lam, mu, iters, xt)
+    gx = (2.0 * (x.double() - xt) / x.numel()).float()
+    gy, gl, gh = plan.backward(y, mask, h, lam, mu, gx)
+    torch.cuda.synchronize()
+    p = probs[0]
+    n = p["M"] * p["N"]
+    k = p["K"] * p["K"]
+    log("oracle adjoint, image 0 (512^2, %d iterations)" % iters)
+    ry, rl, rh = oracle.admm_backward(p["y"].astype(np.float64), explicit_mask(p), p["h"].astype(np.float64),
+                                      float(np.float32(p["lam"])), float(np.float32(p["mu"])), iters,
+                                      gx[:n].cpu().numpy().astype(np.float64).reshape(p["M"], p["N"]))
+    ey = rel_l2(gy[:n].cpu().numpy().astype(np.float64).reshape(p["M"], p["N"]), ry)
+    eh = rel_l2(gh[:k].cpu().numpy().astype(np.float64).reshape(p["K"], p["K"]), rh)
+    el = abs(float(gl[0]) - rl) / max(abs(rl), 1e-30)
+    log("grad_y %.2e grad_h %.2e grad_lambda %.2e" % (ey, eh, el))
+    assert ey <= 1e-3 and eh <= 1e-3 and el <= 1e-3
