@@ -197,6 +197,7 @@ def main():
     unobs = unobserved_fraction(problems)
     inputs = to_device(problems)
     plan = binding.Plan(descs(problems), batched=1, use_graph=1, check_every=args.check_every)
+    log("launch shapes (row, column; 1 = per length, 2 = one launch): %s" % (plan.schedule(),))
     log("timing %d steps (+%d warmup), %d images, %d px, %d iterations" % (args.steps, args.warmup,
                                                                           len(problems), npx, iters))
     t, wall = time_runs(plan, inputs, iters, args.steps, args.warmup)
@@ -245,7 +246,7 @@ def main():
             pl = binding.Plan(descs(bp), check_every=args.check_every, **kw)
             tt, _ = time_runs(pl, binp, bit, 1, 1)
             res[mode] = bnpx * bit / tt / 1e6
-            log("  %s: %.1f Mpx*it/s" % (mode, res[mode]))
+            log("  %s: %.1f Mpx*it/s (launch shapes %s)" % (mode, res[mode], pl.schedule()))
             pl.close()
             torch.cuda.empty_cache()
         extra["batch_256"] = {"mpx_it_s": {k: round(v, 1) for k, v in res.items()},

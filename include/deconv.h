@@ -99,6 +99,12 @@ typedef struct {
   int32_t max_iters;    /* upper bound on iters, sizes the checkpoint store */
   int32_t profile;      /* 1: bracket every row / column pass launched outside a
                            graph with HIP events (read by deconv_plan_kernel_times) */
+  int32_t schedule;     /* batched launch shape of each pass: 0 = autotune at
+                           plan creation (default), 1 = one launch per line
+                           length, 2 = one launch for all lengths */
+  const char* tune_cache; /* nullable: file of autotuning decisions, read before
+                           tuning and appended after (one line per batch
+                           signature) */
 } deconv_options;
 
 typedef struct {
@@ -198,6 +204,11 @@ deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* d
    out[2] = column-pass milliseconds, out[3] = column-pass launches.
    Passes replayed inside a graph are not bracketed. */
 deconv_status deconv_plan_kernel_times(deconv_plan p, double* out);
+
+/* Launch shapes in use (after autotuning): out[0] = row pass, out[1] =
+   column pass, each 1 (one launch per line length) or 2 (one launch for all
+   lengths).  Host call. */
+deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out);
 
 const char* deconv_status_str(deconv_status s);
 

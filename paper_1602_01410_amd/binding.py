@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
                 ("tol_primal", ctypes.c_double), ("tol_dual", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +47,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_create",
            "deconv_plan_destroy", "deconv_admm_run", "deconv_admm_continue", "deconv_state_export",
            "deconv_state_import", "deconv_admm_backward", "deconv_blur_spectrum", "deconv_fft2",
-           "deconv_plan_kernel_times", "deconv_status_str")
+           "deconv_plan_kernel_times", "deconv_plan_schedule", "deconv_status_str")
 
 _lib = None
 
@@ -74,6 +75,7 @@ def lib():
         L.deconv_blur_spectrum.argtypes = [P, P, P]
         L.deconv_fft2.argtypes = [I32, I32, I32, P, I32, P]
         L.deconv_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+        L.deconv_plan_schedule.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         L.deconv_status_str.argtypes = [I32]
         L.deconv_status_str.restype = ctypes.c_char_p
         for f in EXPORTS:
@@ -104,6 +106,8 @@ def default_options(**kw):
     o = Options()
     _check(lib().deconv_options_default(ctypes.byref(o)), "options")
     for k, v in kw.items():
+        if k == "tune_cache" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o
 
@@ -201,6 +205,12 @@ class Plan:
         d = torch.empty(2 * self.npx, dtype=torch.float32, device=device)
         _check(lib().deconv_state_export(self.handle, _ptr(yt), _ptr(v), _ptr(d)), "state_export")
         return yt, v, d
+
+    def schedule(self):
+        """(row, column) launch shapes: 1 = per line length, 2 = one launch."""
+        out = (ctypes.c_int32 * 2)()
+        _check(lib().deconv_plan_schedule(self.handle, out), "schedule")
+        return tuple(out)
 
     def kernel_times(self):
         """(row_ms, row_launches, col_ms, col_launches) since the last call

@@ -14,6 +14,7 @@
 //   vb <- mu D rb,          db <- ub - mu D rb,
 // and the blur gradient collects, in the frequency domain, per frequency k
 //   S_k += conj(QB_k) X_k + conj(Y_k) RB_k - 2 conj(H_k) Re(conj(RB_k) X_k)
+//        = X_k conj(QB_k - H_k RB_k) + RB_k conj(Y_k - H_k X_k)
 // (QB = DFT(alpha M_z^T zb), X = DFT(x), Y = DFT(ytilde^i), RB = DFT(rb));
 // dL/dh[p] = Re(sum_k S_k exp(-2 pi i k.p / N)) / N at the kernel taps.
 //
@@ -60,7 +61,7 @@ struct BwdColArgs {
   const float* mu;
   const float2* tw;
   const float4* fwd_spec;  // (Y, X / (m'n')) stored by the forward recompute
-  float2* S;               // accumulated spectral blur gradient (half, tiled)
+  double2* S;              // accumulated spectral blur gradient (half, tiled, FP64)
 };
 
 // J^T t for the vector soft threshold at u (J is symmetric); also returns the
@@ -252,7 +253,7 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
   const float* __restrict__ dv2 = a.tab + mt.tab;
   const float* __restrict__ dh2 = dv2 + L;
   const float4* __restrict__ fs = a.fwd_spec + base;
-  float2* S = a.S + mt.hh + (long long)blk * L * C;
+  double2* S = a.S + mt.hh + (long long)blk * L * C;
   for (int q = threadIdx.x; q < L * C; q += kNTC) {
     const int ky = q / C, c = q - ky * C;
     const int kx = blk * C + c;
@@ -269,11 +270,15 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
       const float4 f = fs[q];
       const float2 Y = make_float2(f.x, f.y);
       const float2 X = make_float2(f.z * mn, f.w * mn);
-      // conj(QB) X + conj(Y) rb - 2 conj(H) Re(conj(rb) X)
-      const float re = rb.x * X.x + rb.y * X.y;
-      float2 acc = S[q];
-      acc.x += QB.x * X.x + QB.y * X.y + Y.x * rb.x + Y.y * rb.y - 2.f * Hk.x * re;
-      acc.y += QB.x * X.y - QB.y * X.x + Y.x * rb.y - Y.y * rb.x + 2.f * Hk.y * re;
+      // conj(QB) X + conj(Y) rb - 2 conj(H) Re(conj(rb) X), evaluated as
+      // X conj(QB - H rb) + rb conj(Y - H X): the differences are the
+      // spectra of the adjoint and data residuals; accumulated in FP64
+      const float2 hr = cmul(Hk, rb), hx = cmul(Hk, X);
+      const float2 a1 = make_float2(QB.x - hr.x, QB.y - hr.y);
+      const float2 a2 = make_float2(Y.x - hx.x, Y.y - hx.y);
+      double2 acc = S[q];
+      acc.x += (double)X.x * a1.x + (double)X.y * a1.y + (double)rb.x * a2.x + (double)rb.y * a2.y;
+      acc.y += (double)X.y * a1.x - (double)X.x * a1.y + (double)rb.y * a2.x - (double)rb.x * a2.y;
       S[q] = acc;
       R = make_float2(rb.x * scale, rb.y * scale);
       HR = cmul(Hk, R);

@@ -95,42 +95,37 @@ __global__ void __launch_bounds__(kNT) init_adj_c_kernel(const ImgMeta* meta, co
   }
 }
 
-// Hermitian completion of the accumulated half spectrum S into a full
-// complex m' x n' grid (for the final transform to the kernel taps)
-__global__ void unpack_half_kernel(const ImgMeta* meta, const float2* __restrict__ S, float2* grid,
-                                   const long long* goff) {
+// dL/dh[b+p][b+q] = (1/(m'n')) sum_k w(kx) Re(S_k exp(-2 pi i (ky p / m' + kx q / n')))
+// over the stored half spectrum (w = 1 for kx = 0 and kx = n'/2, 2 otherwise:
+// S is Hermitian).  FP64 throughout, with exact phase tables (index products
+// reduced modulo the length); one workgroup per (tap, image).
+__global__ void __launch_bounds__(kNT) grad_taps_kernel(const ImgMeta* meta, const double2* __restrict__ S,
+                                                       const double2* __restrict__ tw64, float* grad_h,
+                                                       const long long* hoff) {
   const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
-  const long long n = (long long)mt.m * mt.n;
-  float2* g = grid + goff[img];
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int ky = (int)(p / mt.n), kx = (int)(p - (long long)ky * mt.n);
-    float2 v;
-    if (kx < mt.nh) {
-      v = S[mt.hh + ((long long)(kx / mt.C) * mt.m + ky) * mt.C + kx % mt.C];
-    } else {
-      const int kx2 = mt.n - kx, ky2 = ky == 0 ? 0 : mt.m - ky;
-      const float2 w = S[mt.hh + ((long long)(kx2 / mt.C) * mt.m + ky2) * mt.C + kx2 % mt.C];
-      v = make_float2(w.x, -w.y);
-    }
-    g[p] = v;
-  }
-}
-
-// dL/dh[b+p][b+q] = Re(F(S))[p mod m', q mod n'] / (m' n')
-__global__ void gather_taps_kernel(const ImgMeta* meta, const float2* grid, const long long* goff,
-                                   const long long* hoff, float* grad_h) {
-  const int img = blockIdx.x;
-  const ImgMeta mt = meta[img];
   const int K = 2 * mt.b + 1;
-  const float2* g = grid + goff[img];
-  const float inv = 1.0f / ((float)mt.m * (float)mt.n);
-  for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
-    const int pp = t / K - mt.b, qq = t % K - mt.b;
-    const int i = ((pp % mt.m) + mt.m) % mt.m, j = ((qq % mt.n) + mt.n) % mt.n;
-    grad_h[hoff[img] + t] = g[(long long)i * mt.n + j].x * inv;
+  const int t = blockIdx.x;
+  if (t >= K * K) return;
+  const int pp = t / K - mt.b, qq = t % K - mt.b;
+  const int pm = pp < 0 ? pp + mt.m : pp, qn = qq < 0 ? qq + mt.n : qq;
+  const double2* TM = tw64 + mt.twc;   // exp(-2 pi i k / m'), k < m'
+  const double2* TN = tw64 + mt.twr;   // exp(-2 pi i k / n'), k < n'
+  double acc = 0.0;
+  const long long tot = (long long)mt.m * mt.nh;
+  for (long long q = threadIdx.x; q < tot; q += kNT) {
+    const int ky = (int)(q / mt.nh), kx = (int)(q - (long long)ky * mt.nh);
+    const double2 sv = S[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))];
+    const double2 a = TM[(int)(((long long)ky * pm) % mt.m)];
+    const double2 b = TN[(int)(((long long)kx * qn) % mt.n)];
+    const double er = a.x * b.x - a.y * b.y, ei = a.x * b.y + a.y * b.x;
+    const double w = (kx == 0 || 2 * kx == mt.n) ? 1.0 : 2.0;
+    acc += w * (sv.x * er - sv.y * ei);
   }
+  __shared__ double red[3 * (kNT / 64)];
+  double z0 = 0, z1 = 0;
+  block_sum3(acc, z0, z1, red);
+  if (threadIdx.x == 0) grad_h[hoff[img] + t] = (float)(acc / ((double)mt.m * (double)mt.n));
 }
 
 // per image: sum of the per-tile dL/dlambda partials

@@ -10,6 +10,10 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <string>
+#include <fstream>
+#include <sstream>
+#include <array>
 #include <new>
 #include <vector>
 #include <cstdint>
@@ -220,7 +224,8 @@ struct deconv_plan_s {
   double* adj_mean = nullptr; // backward: per-block partials of the mean adjoint
   float* adj_z = nullptr;
   float* adj_y = nullptr;
-  float2* adj_S = nullptr;    // accumulated spectral h-gradient (half, tiled)
+  double2* adj_S = nullptr;   // accumulated spectral h-gradient (half, tiled, FP64)
+  double2* tw64 = nullptr;    // FP64 twiddle tables (same offsets as tw), for the tap sums
   double* adj_lam = nullptr;  // per row tile partial of dL/dlambda
   int nck = 0;                // checkpoints stored
 
@@ -228,7 +233,11 @@ struct deconv_plan_s {
   long long total_h = 0;      // packed blur kernel elements
   std::vector<long long> hoff_h;
   std::map<int, long long> tw_off;
-  std::vector<Group> row_groups, col_groups;
+  // batched launch shapes: [0] one group per line length, [1] one group for
+  // all lengths; row_sched / col_sched pick one (autotuned)
+  std::vector<Group> row_sets[2], col_sets[2];
+  int row_sched = 0, col_sched = 0;
+  std::vector<Group> row_groups, col_groups;  // the chosen sets
   std::vector<int4> h_tiles;  // all tile tables, uploaded at plan creation
   std::vector<std::vector<Group>> row_img, col_img;  // per-image launches (batched = 0)
 
@@ -253,7 +262,7 @@ struct Layout {
   size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
       off_part, off_done, off_nonf, off_itd, off_res, off_mean, off_goff, off_hoff, off_hsum;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
-      off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean;
+      off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64;
   size_t total;
 };
 
@@ -264,6 +273,7 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     if (opt->check_every < 0 || opt->ckpt_every < 0 || opt->max_iters < 0) return DECONV_ERR_INVALID_ARG;
     if (opt->tol_primal < 0 || opt->tol_dual < 0) return DECONV_ERR_INVALID_ARG;
     if (opt->ckpt_every > 0 && opt->max_iters <= 0) return DECONV_ERR_INVALID_ARG;
+    if (opt->schedule < 0 || opt->schedule > 2) return DECONV_ERR_INVALID_ARG;
     // the reverse pass replays every iteration: no early stopping with it
     if (opt->ckpt_every > 0 && (opt->tol_primal > 0 || opt->tol_dual > 0)) return DECONV_ERR_INVALID_ARG;
   }
@@ -319,6 +329,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   // and one per image for the per-image launches (batched = 0)
   p->h_tiles.clear();
   p->row_groups.clear(); p->col_groups.clear();
+  for (int k = 0; k < 2; ++k) { p->row_sets[k].clear(); p->col_sets[k].clear(); }
   p->row_img.assign(B, {}); p->col_img.assign(B, {});
   std::vector<std::vector<TileRef>> rt_tiles(B), ct_tiles(B);
   std::set<int> widths, heights;
@@ -341,8 +352,33 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     xcd_schedule(imgs, p->h_tiles);
     dst.push_back(Group{L, t0, (int)((long long)p->h_tiles.size() - t0), lds});
   };
-  add_group(p->row_groups, widths.size() == 1 ? *widths.begin() : 0, rlds, rt_tiles);
-  add_group(p->col_groups, heights.size() == 1 ? *heights.begin() : 0, clds, ct_tiles);
+  add_group(p->row_sets[1], widths.size() == 1 ? *widths.begin() : 0, rlds, rt_tiles);
+  add_group(p->col_sets[1], heights.size() == 1 ? *heights.begin() : 0, clds, ct_tiles);
+  if (widths.size() == 1) {
+    p->row_sets[0] = p->row_sets[1];
+  } else {
+    for (int w : widths) {
+      std::vector<std::vector<TileRef>> sel(B);
+      for (int b = 0; b < B; ++b)
+        if (p->meta[b].n == w) sel[b] = rt_tiles[b];
+      add_group(p->row_sets[0], w, row_lds_bytes(w), sel);
+    }
+  }
+  if (heights.size() == 1) {
+    p->col_sets[0] = p->col_sets[1];
+  } else {
+    for (int h : heights) {
+      std::vector<std::vector<TileRef>> sel(B);
+      for (int b = 0; b < B; ++b)
+        if (p->meta[b].m == h) sel[b] = ct_tiles[b];
+      add_group(p->col_sets[0], h, col_lds_bytes(h), sel);
+    }
+  }
+  const int rs = p->opt.schedule == 1 ? 0 : 1, cs = p->opt.schedule == 1 ? 0 : 1;
+  p->row_sched = rs;
+  p->col_sched = cs;
+  p->row_groups = p->row_sets[rs];
+  p->col_groups = p->col_sets[cs];
   for (int b = 0; b < B; ++b) {
     std::vector<std::vector<TileRef>> one(B);
     one[b] = rt_tiles[b];
@@ -388,7 +424,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     lay.off_adj_b = take(sizeof(float2) * px);
     lay.off_adj_z = take(sizeof(float) * px);
     lay.off_adj_y = take(sizeof(float) * px);
-    lay.off_adj_S = take(sizeof(float2) * hhp);
+    lay.off_adj_S = take(sizeof(double2) * hhp);
+    lay.off_tw64 = take(sizeof(double2) * tw);
     lay.off_adj_lam = take(sizeof(double) * rt);
     lay.off_adj_vb = take(sizeof(float2) * px);
     lay.off_adj_db = take(sizeof(float2) * px);
@@ -396,7 +433,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   } else {
     lay.off_ck_yt = lay.off_ck_v = lay.off_ck_d = lay.off_seg_u = lay.off_seg_spec = 0;
     lay.off_adj_a = lay.off_adj_b = lay.off_adj_z = lay.off_adj_y = lay.off_adj_S = lay.off_adj_lam = 0;
-    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = 0;
+    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = lay.off_tw64 = 0;
   }
   lay.total = o;
 }
@@ -415,6 +452,8 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->ckpt_every = 0;
   opt->max_iters = 0;
   opt->profile = 0;
+  opt->schedule = 0;
+  opt->tune_cache = nullptr;
   return DECONV_OK;
 }
 
@@ -443,6 +482,8 @@ extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
   delete p;
   return DECONV_OK;
 }
+
+static deconv_status autotune(deconv_plan_s* p);
 
 extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, const deconv_image_desc* desc,
                                             const deconv_options* opt, void* stream, void* workspace,
@@ -502,7 +543,8 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
     p->adj_b = at<float2>(w, lay.off_adj_b);
     p->adj_z = at<float>(w, lay.off_adj_z);
     p->adj_y = at<float>(w, lay.off_adj_y);
-    p->adj_S = at<float2>(w, lay.off_adj_S);
+    p->adj_S = at<double2>(w, lay.off_adj_S);
+    p->tw64 = at<double2>(w, lay.off_tw64);
     p->adj_lam = at<double>(w, lay.off_adj_lam);
     p->adj_vb = at<float2>(w, lay.off_adj_vb);
     p->adj_db = at<float2>(w, lay.off_adj_db);
@@ -512,10 +554,20 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   // host-built tables
   const std::vector<int4>& tiles = p->h_tiles;
   std::vector<float2> tw(p->total_tw);
+  std::vector<double2> tw64(p->total_tw);
   for (auto& kv : p->tw_off) {
     std::vector<float2> t;
     twiddles(kv.first, t);
     std::copy(t.begin(), t.end(), tw.begin() + kv.second);
+    for (int k = 0; k < kv.first; ++k) {
+      const double a = -2.0 * M_PI * (double)k / (double)kv.first;
+      tw64[kv.second + k] = make_double2(cos(a), sin(a));
+    }
+  }
+  if (p->tw64 && hipMemcpyAsync(p->tw64, tw64.data(), sizeof(double2) * tw64.size(), hipMemcpyHostToDevice,
+                                 p->stream) != hipSuccess) {
+    deconv_plan_destroy(p);
+    return DECONV_ERR_HIP;
   }
   std::vector<float> tab(p->total_tab);
   std::vector<long long> goff(batch), hoff(batch);
@@ -546,6 +598,8 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
       hipMemsetAsync(p->done, 0, sizeof(int) * batch, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(DECONV_ERR_HIP);
+  deconv_status st = autotune(p);
+  if (st != DECONV_OK) return fail(st);
   *out = p;
   return DECONV_OK;
 }
@@ -672,6 +726,126 @@ static deconv_status launch_cols(deconv_plan_s* p, ColArgs a) {
     HIPCHK(launch_col(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size())));
   }
   timer.done();
+  return DECONV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: per pass, one launch per line length or one launch for all
+// lengths, whichever runs faster on this plan's own workspace
+// ---------------------------------------------------------------------------
+static std::string plan_signature(const deconv_plan_s* p) {
+  std::vector<std::array<int, 5>> v;
+  for (auto& d : p->desc) v.push_back({d.height, d.width, d.ksize, d.mask_kind, 0});
+  std::sort(v.begin(), v.end());
+  std::ostringstream os;
+  os << "gfx950 nt" << kNTR << "/" << kNTC << " rows" << DCV_ROW_PIX << " cols" << DCV_COL_ELEMS << " |";
+  for (size_t i = 0; i < v.size();) {
+    size_t j = i;
+    while (j < v.size() && v[j] == v[i]) ++j;
+    os << " " << v[i][0] << "x" << v[i][1] << "k" << v[i][2] << "m" << v[i][3] << "*" << (j - i);
+    i = j;
+  }
+  return os.str();
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int* r, int* c) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const size_t t1 = line.find('\t');
+    if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size()) continue;
+    int rr = 0, cc = 0;
+    if (sscanf(line.c_str() + t1 + 1, "%d %d", &rr, &cc) == 2 && rr >= 0 && rr <= 1 && cc >= 0 && cc <= 1) {
+      *r = rr;
+      *c = cc;
+      found = true;   // the last entry wins
+    }
+  }
+  return found;
+}
+
+static void cache_store(const char* path, const std::string& key, int r, int c) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << "\t" << r << " " << c << "\n";
+}
+
+static deconv_status autotune(deconv_plan_s* p) {
+  if (p->opt.schedule != 0 || !p->opt.batched) return DECONV_OK;
+  const bool rows = p->row_sets[0].size() > 1, cols = p->col_sets[0].size() > 1;
+  if (!rows && !cols) return DECONV_OK;
+  const std::string key = plan_signature(p);
+  int rs = 1, cs = 1;
+  if (!cache_lookup(p->opt.tune_cache, key, &rs, &cs)) {
+    hipStream_t s = p->stream;
+    const size_t n = (size_t)p->total_px;
+    HIPCHK(hipMemsetAsync(p->yt, 0, sizeof(float) * n, s));
+    HIPCHK(hipMemsetAsync(p->v, 0, sizeof(float2) * n, s));
+    HIPCHK(hipMemsetAsync(p->dbuf[0], 0, sizeof(float2) * n, s));
+    HIPCHK(hipMemsetAsync(p->dbuf[1], 0, sizeof(float2) * n, s));
+    // lambda = 0, mu = 1 and an all-unobserved mask: any finite data will do
+    float* par = nullptr;
+    uint8_t* msk = nullptr;
+    HIPCHK(hipMalloc(&par, sizeof(float) * 2 * p->batch));
+    if (hipMalloc(&msk, n) != hipSuccess) { (void)hipFree(par); return DECONV_ERR_OOM; }
+    std::vector<float> hp(2 * p->batch, 0.f);
+    for (int b = 0; b < p->batch; ++b) hp[p->batch + b] = 1.f;
+    deconv_status st = DECONV_OK;
+    double best[2][2] = {{0, 0}, {0, 0}};
+    if (hipMemcpy(par, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(msk, 0, n, s) != hipSuccess) st = DECONV_ERR_HIP;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == DECONV_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+      st = DECONV_ERR_HIP;
+    const int kReps = 4;
+    for (int pass = 0; pass < 2 && st == DECONV_OK; ++pass) {
+      for (int k = 0; k < 2 && st == DECONV_OK; ++k) {
+        if (pass == 0) p->row_groups = p->row_sets[k];
+        else p->col_groups = p->col_sets[k];
+        for (int r = 0; r <= kReps && st == DECONV_OK; ++r) {
+          if (r == 1 && hipEventRecord(e0, s) != hipSuccess) st = DECONV_ERR_HIP;
+          if (pass == 0) {
+            RowArgs a = row_args(p, msk, par, par + p->batch);
+            a.mode = ROW_ITER;
+            a.d_in = p->dbuf[0];
+            a.d_out = p->dbuf[1];
+            a.done = nullptr;
+            if (st == DECONV_OK) st = launch_rows(p, a);
+          } else {
+            ColArgs a = col_args(p, par + p->batch);
+            a.done = nullptr;
+            if (st == DECONV_OK) st = launch_cols(p, a);
+          }
+        }
+        float ms = 0.f;
+        if (st == DECONV_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = DECONV_ERR_HIP;
+        best[pass][k] = ms;
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(msk);
+    (void)hipFree(par);
+    if (st != DECONV_OK) return st;
+    rs = rows ? (best[0][0] < best[0][1] ? 0 : 1) : 1;
+    cs = cols ? (best[1][0] < best[1][1] ? 0 : 1) : 1;
+    cache_store(p->opt.tune_cache, key, rs, cs);
+  }
+  p->row_sched = rs;
+  p->col_sched = cs;
+  p->row_groups = p->row_sets[rs];
+  p->col_groups = p->col_sets[cs];
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  out[0] = p->row_sched + 1;
+  out[1] = p->col_sched + 1;
   return DECONV_OK;
 }
 

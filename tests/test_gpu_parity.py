@@ -198,3 +198,23 @@ def test_error_paths(torch_cuda):
     with pytest.raises(binding.DeconvError) as e:
         binding.Plan([dict(height=64, width=64, ksize=4)])
     assert e.value.code == 2
+
+
+def test_autotuned_schedules_agree(tmp_path):
+    """Both launch shapes (one launch per line length, one launch for all)
+    give the same iterates; the autotuner records its choice in the cache and
+    a second plan for the same batch reuses it."""
+    from paper_1602_01410_amd import binding
+    probs = _mixed(seed0=80)
+    a = gpu_run(probs, 12, schedule=1)
+    b = gpu_run(probs, 12, schedule=2)
+    for i in range(len(probs)):
+        assert rel_l2(a["x"][i], b["x"][i]) <= 1e-6
+    assert a["plan"].schedule() == (1, 1) and b["plan"].schedule() == (2, 2)
+    cache = str(tmp_path / "tune.txt")
+    p1 = binding.Plan([desc(p) for p in probs], tune_cache=cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and "\t" in lines[0]
+    p2 = binding.Plan([desc(p) for p in probs], tune_cache=cache)
+    assert p2.schedule() == p1.schedule()
+    assert len(open(cache).read().splitlines()) == 1
