@@ -86,7 +86,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 2) * LS, a.tw + mt.twr);
+  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
   const int npx = (nr + 1) * L;
@@ -95,10 +95,10 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   float lsum = 0.f;
 
   if (a.mode != BWD_START) {
-    // finish reverse step: rb + i H rb on rows r0-1 .. r0+nr
-    gather_rows<L, RT + 2>(a.spec_in + mt.sp, buf, M, r0, nr + 2, nh, nb, C, logC);
+    // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
+    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
     __syncthreads();
-    fft_lines<L, true, kNTR, RT + 2>(buf, nr + 2, tw);
+    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
   }
 
 #pragma unroll
@@ -114,11 +114,11 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
         vbv = a.vb[pix];
         dbv = a.db[pix];
       } else {
-        const float2 c0 = buf[l * LS + lpad(j)];
-        const float r = c0.x;
-        hr = c0.y;
-        const float rr = buf[l * LS + lpad(j + 1 == L ? 0 : j + 1)].x;
-        const float rd = buf[(l + 1) * LS + lpad(j)].x;
+        const int lj = lpad(j);
+        const float r = row_x<LS>(buf, l, nr, lj);
+        if (l >= 1) hr = buf[(l - 1) * LS + lj].y;
+        const float rr = row_x<LS>(buf, l, nr, lpad(j + 1 == L ? 0 : j + 1));
+        const float rd = row_x<LS>(buf, l + 1, nr, lj);
         const float2 ubo = a.ub_in[pix];
         vbv = make_float2(mu * (rr - r), mu * (rd - r));
         dbv = make_float2(ubo.x - vbv.x, ubo.y - vbv.y);
@@ -165,43 +165,12 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   }
 
   // start the next reverse step: xb = D^T ub (+ grad_x), qb, forward row DFT
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
-      buf[l * LS + lpad(j)] = ureg[k];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
-      if (l >= 1) {
-        const float2 w = buf[l * LS + lpad(j)];
-        const float whl = buf[l * LS + lpad(j == 0 ? L - 1 : j - 1)].x;
-        const float wvu = buf[(l - 1) * LS + lpad(j)].y;
-        float xb = whl - w.x + wvu - w.y;
-        if (a.grad_x) xb += a.grad_x[mt.px + (long long)(r0 - 1 + l) * L + j];
-        ureg[k] = make_float2(xb, qreg[k]);
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
-      if (l >= 1) buf[l * LS + lpad(j)] = ureg[k];
-    }
-  }
-  __syncthreads();
-  fft_lines<L, false, kNTR, RT>(buf + LS, nr, tw);
-  split_store<L, RT>(a.spec_out + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+  const float* __restrict__ gx = a.grad_x ? a.grad_x + mt.px : nullptr;
+  row_prologue<L, RT, KP>(buf, ureg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
+                          [&](int k, int l, int j, float g) {
+                            const float xb = gx ? g + gx[(r0 - 1 + l) * L + j] : g;
+                            return make_float2(xb, qreg[k]);
+                          });
 }
 
 template <int L>

@@ -67,7 +67,12 @@ __host__ __device__ constexpr int c_for(int L) {
 #define DCV_TW_GLOBAL 1
 #endif
 constexpr int kTwLds = DCV_TW_GLOBAL ? 0 : 1;
-__host__ __device__ constexpr int row_lds_elems(int L) { return (rt_for(L) + 2) * lstride(L) + kTwLds * L; }
+// row pass: issue the epilogue's state loads before the inverse transform
+// (1) or after it (0, fewer live registers)
+#ifndef DCV_EARLY_STATE
+#define DCV_EARLY_STATE 1
+#endif
+__host__ __device__ constexpr int row_lds_elems(int L) { return (rt_for(L) + 1) * lstride(L) + kTwLds * L; }
 __host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLds * L; }
 
 // the twiddle table a workgroup uses for length L (caller synchronises)
@@ -148,6 +153,24 @@ __device__ __forceinline__ bool observed(const ImgMeta& mt, const uint8_t* __res
   return in_c;
 }
 
+// The same test split into a per-row part (uniform over a row) and a
+// branch-free per-pixel part.
+struct RowObs {
+  bool explicit_mask, decim, row_ok;
+};
+__device__ __forceinline__ RowObs row_observed(const ImgMeta& mt, int i) {
+  RowObs r;
+  r.explicit_mask = mt.mask_kind == 1;
+  r.decim = mt.mask_kind == 2 && mt.decim > 1;
+  r.row_ok = (i >= mt.b) & (i < mt.m - mt.b) & (!r.decim | divisible(i - mt.b, mt.decim, mt.dmagic));
+  return r;
+}
+__device__ __forceinline__ bool pixel_observed(const ImgMeta& mt, const RowObs& r,
+                                               const uint8_t* __restrict__ mask_row, int j) {
+  if (r.explicit_mask) return mask_row[j] != 0;
+  return r.row_ok & (j >= mt.b) & (j < mt.n - mt.b) & (!r.decim | divisible(j - mt.b, mt.decim, mt.dmagic));
+}
+
 __device__ __forceinline__ int wrapi(int i, int M) { return i < 0 ? i + M : (i >= M ? i - M : i); }
 
 // reciprocal with one Newton step (error below 1 ulp of the exact division)
@@ -180,15 +203,22 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // row pass
 // ---------------------------------------------------------------------------
 
-// Gather X + iQ for lines 0..nl-1 (image rows r0-1 .. r0+nl-2, periodic) from
-// the tiled half spectra into LDS, completing the other half by Hermitian
-// symmetry.  All loads of a thread are issued before any LDS write.
-template <int L, int NLMAX>
-__device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nl,
+// LDS lines of a row tile with nr own rows: lines 0..nr-1 hold the own rows
+// r0..r0+nr-1 (x + iHx after the inverse transform); line nr holds the two
+// halo rows packed as one complex line, x(r0-1) + i x(r0+nr).  Only x is
+// needed on the halo rows, so both share one transform.
+//
+// Gather the tile's half spectra from the tiled layout into those lines,
+// completing the other half by Hermitian symmetry: X + iQ for the own rows,
+// X(r0-1) + i X(r0+nr) for the halo line.  All loads are issued first.
+template <int L, int RT>
+__device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC) {
   constexpr int LS = lstride(L);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
-  constexpr int NQ = (NLMAX * NBC_MAX + kNTR - 1) / kNTR;
+  constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
+  constexpr int NH = (NBC_MAX + kNTR - 1) / kNTR;
+  const float2* __restrict__ sin2 = reinterpret_cast<const float2*>(sin);
   float4 g[NQ];
   int dst[NQ];
 #pragma unroll
@@ -196,14 +226,25 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
     const int q = threadIdx.x + k * kNTR;
     const int c = q & (C - 1);
     const int t2 = q >> logC;
-    const int l = t2 % NLMAX, blk = t2 / NLMAX;
+    const int l = t2 % RT, blk = t2 / RT;
     const int kx = blk * C + c;
     dst[k] = -1;
-    if (l < nl && blk < nb && kx < nh) {
-      int i = r0 - 1 + l;
-      i = i < 0 ? i + M : (i >= M ? i - M : i);
-      g[k] = sin[(blk * M + i) * C + c];
+    if (l < nr && blk < nb && kx < nh) {
+      g[k] = sin[((__umul24(blk, M) + r0 + l) << logC) + c];
       dst[k] = l * LS + kx;
+    }
+  }
+  const int ia = r0 == 0 ? M - 1 : r0 - 1;
+  const int ib = r0 + nr == M ? 0 : r0 + nr;
+  float2 ha[NH], hb[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int q = threadIdx.x + k * kNTR;
+    const int c = q & (C - 1), blk = q >> logC;
+    if (blk < nb && blk * C + c < nh) {
+      const unsigned base = __umul24(blk, M);
+      ha[k] = sin2[2 * (((base + ia) << logC) + c)];
+      hb[k] = sin2[2 * (((base + ib) << logC) + c)];
     }
   }
 #pragma unroll
@@ -216,9 +257,32 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
       if (kx >= 1 && kx <= L - nh) line[lpad(L - kx)] = make_float2(v.x + v.w, v.z - v.y);
     }
   }
+  float2* hline = buf + nr * LS;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int q = threadIdx.x + k * kNTR;
+    const int c = q & (C - 1), blk = q >> logC;
+    const int kx = blk * C + c;
+    if (blk < nb && kx < nh) {
+      hline[lpad(kx)] = make_float2(ha[k].x - hb[k].y, ha[k].y + hb[k].x);
+      if (kx >= 1 && kx <= L - nh) hline[lpad(L - kx)] = make_float2(ha[k].x + hb[k].y, hb[k].x - ha[k].y);
+    }
+  }
 }
 
-// Split C = F(a) + i F(b) of lines 1..nr into the half spectra of the real
+// LDS slot of tile row l (image row r0-1+l, l = 0..nr+1): the halo line for
+// l = 0 and l = nr+1, own line l-1 otherwise.
+__device__ __forceinline__ int row_slot(int l, int nr) { return (l == 0 || l == nr + 1) ? nr : l - 1; }
+
+// x on tile row l (real part of the own line, or the halo line's real part
+// for the row above and imaginary part for the row below)
+template <int LS>
+__device__ __forceinline__ float row_x(const float2* buf, int l, int nr, int lj) {
+  const float2 v = buf[row_slot(l, nr) * LS + lj];
+  return l == nr + 1 ? v.y : v.x;
+}
+
+// Split C = F(a) + i F(b) of lines 0..nr-1 into the half spectra of the real
 // signals a, b and store them in the tiled layout.
 template <int L, int RT>
 __device__ __forceinline__ void split_store(float4* __restrict__ sout, const float2* buf, int M, int r0, int nr,
@@ -234,92 +298,180 @@ __device__ __forceinline__ void split_store(float4* __restrict__ sout, const flo
     const int l = t2 % RT, blk = t2 / RT;
     const int kx = blk * C + c;
     if (l < nr && blk < nb && kx < nh) {
-      const float2 cf = buf[(l + 1) * LS + lpad(kx)];
-      const float2 cm = buf[(l + 1) * LS + lpad(kx == 0 ? 0 : L - kx)];
-      sout[(blk * M + r0 + l) * C + c] =
+      const float2 cf = buf[l * LS + lpad(kx)];
+      const float2 cm = buf[l * LS + lpad(kx == 0 ? 0 : L - kx)];
+      sout[((__umul24(blk, M) + r0 + l) << logC) + c] =
           make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
     }
   }
 }
 
+// Pixel p = tid + k * kNTR of a row tile sits on tile row p / L, column p % L.
+// When L is a multiple of the workgroup size the row is a compile-time
+// function of k; when the workgroup covers whole rows it is a shift.
 template <int L>
+struct PixMap {
+  static constexpr bool kSplitRow = L % kNTR == 0;
+  static constexpr bool kWholeRows = !kSplitRow && kNTR % L == 0;
+  __device__ static __forceinline__ int row(int k, unsigned tid) {
+    if constexpr (kSplitRow) return k / (L / kNTR);
+    else if constexpr (kWholeRows) return k * (kNTR / L) + (int)(tid / L);
+    else return (int)((tid + k * kNTR) / L);
+  }
+  __device__ static __forceinline__ int col(int k, unsigned tid) {
+    if constexpr (kSplitRow) return (k % (L / kNTR)) * kNTR + (int)tid;
+    else if constexpr (kWholeRows) return (int)(tid % L);
+    else return (int)((tid + k * kNTR) % L);
+  }
+};
+
+// Start of the next transform: with a vector field w of tile rows 0..nr in
+// wreg, form g = D^T w on the own rows, pack(k, l, j, g) into the own lines,
+// transform them forward and store their split half spectra.
+template <int L, int RT, int KP, class Pack>
+__device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], int nr, const float2* tw,
+                                             float4* __restrict__ sout, int M, int r0, int nh, int nb, int C,
+                                             int logC, Pack pack) {
+  using PM = PixMap<L>;
+  constexpr int LS = lstride(L);
+  const unsigned tid = threadIdx.x;
+  __builtin_assume(tid < (unsigned)kNTR);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l <= nr) buf[row_slot(l, nr) * LS + lpad(j)] = wreg[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l <= nr && l >= 1) {
+      const float2* line = buf + (l - 1) * LS;
+      const float2 w = line[lpad(j)];
+      const float whl = line[lpad(j == 0 ? L - 1 : j - 1)].x;
+      const float wvu = buf[row_slot(l - 1, nr) * LS + lpad(j)].y;
+      wreg[k] = pack(k, l, j, whl - w.x + wvu - w.y);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l <= nr && l >= 1) buf[(l - 1) * LS + lpad(j)] = wreg[k];
+  }
+  __syncthreads();
+  fft_lines<L, false, kNTR, RT>(buf, nr, tw);
+  split_store<L, RT>(sout, buf, M, r0, nr, nh, nb, C, logC);
+}
+
+// Vector soft threshold factor: max(|u| - tau, 0) / |u| for |u|^2 = n2,
+// 0 when |u| <= tau (including u = 0).
+__device__ __forceinline__ float vsoft_scale(float n2, float tau, float tau2) {
+  return n2 > tau2 ? 1.0f - tau * __builtin_amdgcn_rsqf(n2) : 0.f;
+}
+
+// PLAIN: an iteration that neither checks residuals nor stores v, x or u
+// (most iterations between two residual checks); the flags are then
+// compile-time constants.
+template <int L, bool PLAIN>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
+  using PM = PixMap<L>;
   constexpr int RT = rt_for(L);
   constexpr int LS = lstride(L);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;  // pixels per thread (own rows + 1 halo)
+  const unsigned tid = threadIdx.x;
+  __builtin_assume(tid < (unsigned)kNTR);
   const ImgMeta mt = a.meta[img];
   const int M = mt.m;
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
+  const bool check = !PLAIN && a.check;
+  const bool store_v = !PLAIN && a.store_v;
+  const bool store_x = !PLAIN && a.store_x;
   // image-local bases (uniform) with 32-bit offsets below
   const float2* __restrict__ d_in = a.d_in + mt.px;
   float2* __restrict__ d_out = a.d_out + mt.px;
   float* __restrict__ yt = a.yt + mt.px;
   float2* __restrict__ vst = a.v + mt.px;
-  float* __restrict__ x_out = a.x_out ? a.x_out + mt.px : nullptr;
-  float2* __restrict__ u_out = a.u_out ? a.u_out + mt.px : nullptr;
+  float* __restrict__ x_out = store_x ? a.x_out + mt.px : nullptr;
+  float2* __restrict__ u_out = (!PLAIN && a.u_out) ? a.u_out + mt.px : nullptr;
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 2) * LS, a.tw + mt.twr);
+  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
-  const int npx = (nr + 1) * L;   // rows r0-1 .. r0+nr-1
+  const float tau2 = tau * tau;
+  const float alpha = a.alpha;
   float ynew[KP];
   float2 wreg[KP];
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
-  if (a.mode == ROW_ITER) {
-    gather_rows<L, RT + 2>(a.spec_in + mt.sp, buf, M, r0, nr + 2, nh, nb, C, logC);
+  if (PLAIN || a.mode == ROW_ITER) {
+    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+    __syncthreads();
+#if DCV_EARLY_STATE
     // state loads for the epilogue, issued before the transform
     float2 dd[KP];
     float yo[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = threadIdx.x + k * kNTR;
-      if (p < npx) {
-        const int l = p / L, j = p - l * L;
-        const int i = wrapi(r0 - 1 + l, M);
-        const int pix = i * L + j;
+      const int l = PM::row(k, tid), j = PM::col(k, tid);
+      if (l <= nr) {
+        const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
         dd[k] = d_in[pix];
         if (l >= 1) yo[k] = yt[pix];
       }
     }
-    __syncthreads();
-    fft_lines<L, true, kNTR, RT + 2>(buf, nr + 2, tw);
-
-    // epilogue: z-step, TV prox, dual update for rows r0-1 .. r0+nr-1
+    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+#else
+    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+    float2 dd[KP];
+    float yo[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = threadIdx.x + k * kNTR;
-      if (p < npx) {
-        const int l = p / L, j = p - l * L;
+      const int l = PM::row(k, tid), j = PM::col(k, tid);
+      if (l <= nr) {
+        const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
+        dd[k] = d_in[pix];
+        if (l >= 1) yo[k] = yt[pix];
+      }
+    }
+#endif
+
+    // epilogue: z-step, TV prox, dual update for tile rows 0..nr
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int l = PM::row(k, tid), j = PM::col(k, tid);
+      if (l <= nr) {
         const int i = wrapi(r0 - 1 + l, M);
-        const float2 c0 = buf[l * LS + lpad(j)];
-        const float x = c0.x;
-        const float xr = buf[l * LS + lpad(j + 1 == L ? 0 : j + 1)].x;
-        const float xd = buf[(l + 1) * LS + lpad(j)].x;
-        const int pix = i * L + j;
+        const unsigned pix = (unsigned)(i * L + j);
+        const int lj = lpad(j), ljr = lpad(j + 1 == L ? 0 : j + 1);
+        const float x = row_x<LS>(buf, l, nr, lj);
+        const float xr = row_x<LS>(buf, l, nr, ljr);
+        const float xd = row_x<LS>(buf, l + 1, nr, lj);
         const float uh = xr - x + dd[k].x, uv = xd - x + dd[k].y;
-        const float nrm = sqrtf(uh * uh + uv * uv);
-        const float s = nrm > tau ? 1.0f - tau * frcp(nrm) : 0.f;
-        const float vh = s * uh, vv = s * uv;
+        const float sc = vsoft_scale(uh * uh + uv * uv, tau, tau2);
+        const float vh = sc * uh, vv = sc * uv;
         const float dh = uh - vh, dv = uv - vv;
         wreg[k] = make_float2(vh - dh, vv - dv);
         if (l >= 1) {
           d_out[pix] = make_float2(dh, dv);
-          rd += (dh - dd[k].x) * (dh - dd[k].x) + (dv - dd[k].y) * (dv - dd[k].y);
-          if (a.check) {
+          if (check) {
+            rd += (dh - dd[k].x) * (dh - dd[k].x) + (dv - dd[k].y) * (dv - dd[k].y);
             const float2 vo = vst[pix];
             rv += (vh - vo.x) * (vh - vo.x) + (vv - vo.y) * (vv - vo.y);
           }
-          if (a.store_v) vst[pix] = make_float2(vh, vv);
+          if (store_v) vst[pix] = make_float2(vh, vv);
           float yn = yo[k];
-          if (!observed(mt, a.mask, i, j)) {
-            yn = yo[k] + a.alpha * (c0.y - yo[k]);
+          const RowObs ro = row_observed(mt, i);
+          if (!pixel_observed(mt, ro, ro.explicit_mask ? a.mask + mt.px + i * L : nullptr, j)) {
+            const float hx = buf[(l - 1) * LS + lj].y;
+            yn = yo[k] + alpha * (hx - yo[k]);
             yt[pix] = yn;
-            rz += (yn - yo[k]) * (yn - yo[k]);
+            if (check) rz += (yn - yo[k]) * (yn - yo[k]);
           }
           ynew[k] = yn;
-          if (a.store_x) x_out[pix] = x;
+          if (store_x) x_out[pix] = x;
           if (u_out) u_out[pix] = make_float2(uh, uv);
         }
       }
@@ -328,11 +480,9 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
     // ROW_STATE: start from a stored state (v, d, ytilde)
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = threadIdx.x + k * kNTR;
-      if (p < npx) {
-        const int l = p / L, j = p - l * L;
-        const int i = wrapi(r0 - 1 + l, M);
-        const int pix = i * L + j;
+      const int l = PM::row(k, tid), j = PM::col(k, tid);
+      if (l <= nr) {
+        const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
         const float2 vv = vst[pix], dd = d_in[pix];
         wreg[k] = make_float2(vv.x - dd.x, vv.y - dd.y);
         if (l >= 1) {
@@ -343,7 +493,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
     }
   }
 
-  if (a.check) {
+  if (check) {
     __shared__ double red[3 * (kNTR / 64)];
     double rdd = rd, rvd = rv, rzd = rz;
     block_sum3(rdd, rvd, rzd, red);
@@ -352,72 +502,41 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
       out[0] = rdd; out[1] = rvd; out[2] = rzd;
     }
   }
-  if (a.last) return;
-
-  // prologue of the next x-step: g = D^T w with w = v - d, pack ytilde + i mu g
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
-      buf[l * LS + lpad(j)] = wreg[k];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
-      if (l >= 1) {
-        const float2 w = buf[l * LS + lpad(j)];
-        const float whl = buf[l * LS + lpad(j == 0 ? L - 1 : j - 1)].x;
-        const float wvu = buf[(l - 1) * LS + lpad(j)].y;
-        wreg[k] = make_float2(ynew[k], mu * (whl - w.x + wvu - w.y));
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
-      if (l >= 1) buf[l * LS + lpad(j)] = wreg[k];
-    }
-  }
-  __syncthreads();
-  fft_lines<L, false, kNTR, RT>(buf + LS, nr, tw);
-  split_store<L, RT>(a.spec_out + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+  if (!PLAIN && a.last) return;
+  // prologue of the next x-step: pack ytilde + i mu D^T(v - d)
+  row_prologue<L, RT, KP>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
+                          [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); });
 }
 
 // Tile tables are built on the host in dispatch order (XCD-interleaved, see
 // deconv.hip); entries with image -1 are padding.
-template <int L>
-__global__ void __launch_bounds__(kNTR) row_kernel(RowArgs a) {
+#ifndef DCV_ROW_WAVES
+#define DCV_ROW_WAVES 1
+#endif
+template <int L, bool PLAIN>
+__global__ void __launch_bounds__(kNTR, DCV_ROW_WAVES) row_kernel(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  row_tile<L>(a, t.x, t.y, lds);
+  row_tile<L, PLAIN>(a, t.x, t.y, lds);
 }
 
 // one launch for tiles of every line length: dispatch on the tile's length
-template <int L0, int... Ls>
+template <bool PLAIN, int L0, int... Ls>
 __device__ __forceinline__ void row_dispatch(const RowArgs& a, int L, int img, int r0, float2* lds) {
   if (L == L0) {
-    row_tile<L0>(a, img, r0, lds);
+    row_tile<L0, PLAIN>(a, img, r0, lds);
     return;
   }
-  if constexpr (sizeof...(Ls) > 0) row_dispatch<Ls...>(a, L, img, r0, lds);
+  if constexpr (sizeof...(Ls) > 0) row_dispatch<PLAIN, Ls...>(a, L, img, r0, lds);
 }
 
-template <int... Ls>
+template <bool PLAIN, int... Ls>
 __global__ void __launch_bounds__(kNTR) row_kernel_multi(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  row_dispatch<Ls...>(a, a.meta[t.x].n, t.x, t.y, lds);
+  row_dispatch<PLAIN, Ls...>(a, a.meta[t.x].n, t.x, t.y, lds);
 }
 
 // ---------------------------------------------------------------------------

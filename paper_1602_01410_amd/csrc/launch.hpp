@@ -39,11 +39,15 @@ inline hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void
   return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(nt), args, lds, s);
 }
 
-// L = 0 launches the kernel that dispatches on each tile's length
+// L = 0 launches the kernel that dispatches on each tile's length.
+// launch_row picks the plain-iteration instantiation when the arguments ask
+// for no residuals and no stores of v, x or u.
 size_t row_lds_bytes(int L);
 size_t col_lds_bytes(int L);
 hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
+hipError_t launch_row_plain(int L, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
+                            hipEvent_t e1);
 hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a);

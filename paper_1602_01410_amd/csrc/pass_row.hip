@@ -13,10 +13,12 @@ size_t row_lds_bytes(int L) {
 }
 
 hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0, hipEvent_t e1) {
+  const bool plain = a.mode == ROW_ITER && !a.check && !a.store_v && !a.store_x && !a.u_out && !a.last;
+  if (plain) return launch_row_plain(L, grid, lds, s, a, e0, e1);
   void* args[] = {&a};
-  if (L == 0) return launch_lds(row_kernel_multi<DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
+  if (L == 0) return launch_lds(row_kernel_multi<false, DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
   switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(row_kernel<n>, grid, lds, s, args, kNTR, e0, e1);
+#define DCV_CASE(n) case n: return launch_lds(row_kernel<n, false>, grid, lds, s, args, kNTR, e0, e1);
     DCV_FOR_EACH_LEN(DCV_CASE)
 #undef DCV_CASE
   }
