@@ -95,7 +95,8 @@ typedef struct {
   int32_t batched;      /* 1: one launch per phase for all images of a length
                            (default); 0: one launch per image per phase */
   int32_t ckpt_every;   /* keep the state every k iterations for the backward
-                           pass (0 = no backward support) */
+                           pass (0 = no backward support); needs bgs_passes = 1,
+                           adapt_t = 0 and warm_iters = 0 */
   int32_t max_iters;    /* upper bound on iters, sizes the checkpoint store */
   int32_t profile;      /* 1: bracket every row / column pass launched outside a
                            graph with HIP events (read by deconv_plan_kernel_times) */
@@ -105,6 +106,16 @@ typedef struct {
   const char* tune_cache; /* nullable: file of autotuning decisions, read before
                            tuning and appended after (one line per batch
                            signature) */
+  int32_t bgs_passes;   /* block-Gauss-Seidel passes of the x- and z-steps per
+                           iteration, v and d frozen between them (Sec. III-B;
+                           "Proposed-AD" takes b of a (2b+1)^2 blur).  Default 1. */
+  double adapt_t;       /* > 0: adapt mu every iteration with threshold t and
+                           rescale d (eq. (varying_penalty), t = 3 in Sec.
+                           III-B); 0 = fixed mu (default) */
+  int32_t warm_iters;   /* > 0: start z from that many steps of the quadratic
+                           warm start of eqs. (ini_x), (ini_z) (Sec. III-B uses
+                           100); 0 = edge replication only (default) */
+  float warm_tau;       /* tau of the warm start (default 1e-3) */
 } deconv_options;
 
 typedef struct {
@@ -113,6 +124,8 @@ typedef struct {
   double r_dual;        /* |v' - v| at the last check */
   double r_z;           /* |z' - z| at the last check */
   int32_t status;       /* DECONV_OK or DECONV_ERR_NONFINITE */
+  float mu;             /* penalty after the last iteration (differs from the
+                           input only with opt.adapt_t > 0) */
 } deconv_stats;
 
 /* Fill *opt with the defaults above. */

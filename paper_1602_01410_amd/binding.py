@@ -36,12 +36,15 @@ class Options(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("bgs_passes", ctypes.c_int32),
+                ("adapt_t", ctypes.c_double), ("warm_iters", ctypes.c_int32),
+                ("warm_tau", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iters_done", ctypes.c_int32), ("r_primal", ctypes.c_double),
-                ("r_dual", ctypes.c_double), ("r_z", ctypes.c_double), ("status", ctypes.c_int32)]
+                ("r_dual", ctypes.c_double), ("r_z", ctypes.c_double), ("status", ctypes.c_int32),
+                ("mu", ctypes.c_float)]
 
 
 EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_create",
@@ -105,7 +108,10 @@ def _stream_ptr(stream):
 def default_options(**kw):
     o = Options()
     _check(lib().deconv_options_default(ctypes.byref(o)), "options")
+    names = {f[0] for f in Options._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError("unknown option %r" % k)
         if k == "tune_cache" and isinstance(v, str):
             v = v.encode()
         setattr(o, k, v)
@@ -168,8 +174,8 @@ class Plan:
     def _stats_list(st):
         if st is None:
             return None
-        return [dict(iters_done=s.iters_done, r_primal=s.r_primal, r_dual=s.r_dual, r_z=s.r_z, status=s.status)
-                for s in st]
+        return [dict(iters_done=s.iters_done, r_primal=s.r_primal, r_dual=s.r_dual, r_z=s.r_z, status=s.status,
+                     mu=s.mu) for s in st]
 
     def run(self, y, mask, h, lam, mu, iters, x_out=None, ytilde_out=None, stats=False):
         dev = y.device

@@ -211,6 +211,8 @@ struct deconv_plan_s {
   long long* goff = nullptr;
   long long* hoff = nullptr;
   float2* hsum = nullptr;     // DC term of each spectrum (host check)
+  float* mu_cur = nullptr;    // adaptive penalty: current mu per image
+  float* dscale = nullptr;    // adaptive penalty: rescale of d per image
   // backward support
   float* ck_yt = nullptr;     // checkpoints: ytilde, v, d per stored iteration
   float2* ck_v = nullptr;
@@ -260,7 +262,8 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
-      off_part, off_done, off_nonf, off_itd, off_res, off_mean, off_goff, off_hoff, off_hsum;
+      off_part, off_done, off_nonf, off_itd, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
+      off_dscale;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
       off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64;
   size_t total;
@@ -276,6 +279,13 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     if (opt->schedule < 0 || opt->schedule > 2) return DECONV_ERR_INVALID_ARG;
     // the reverse pass replays every iteration: no early stopping with it
     if (opt->ckpt_every > 0 && (opt->tol_primal > 0 || opt->tol_dual > 0)) return DECONV_ERR_INVALID_ARG;
+    if (opt->bgs_passes < 1 || opt->bgs_passes > 64) return DECONV_ERR_INVALID_ARG;
+    if (!(opt->adapt_t >= 0.0) || opt->warm_iters < 0) return DECONV_ERR_INVALID_ARG;
+    if (opt->warm_iters > 0 && !(opt->warm_tau > 0.f)) return DECONV_ERR_INVALID_ARG;
+    // the reverse pass is derived for one pass, a fixed penalty and the plain
+    // initial state
+    if (opt->ckpt_every > 0 && (opt->bgs_passes != 1 || opt->adapt_t > 0 || opt->warm_iters > 0))
+      return DECONV_ERR_INVALID_ARG;
   }
   for (int b = 0; b < batch; ++b) {
     const deconv_image_desc& d = desc[b];
@@ -412,6 +422,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   lay.off_goff = take(sizeof(long long) * B);
   lay.off_hoff = take(sizeof(long long) * B);
   lay.off_hsum = take(sizeof(float2) * B);
+  lay.off_mu = take(sizeof(float) * B);
+  lay.off_dscale = take(sizeof(float) * B);
   const int ck = p->opt.ckpt_every;
   if (ck > 0) {
     const int nck = (p->opt.max_iters + ck - 1) / ck + 1;
@@ -454,6 +466,10 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->profile = 0;
   opt->schedule = 0;
   opt->tune_cache = nullptr;
+  opt->bgs_passes = 1;
+  opt->adapt_t = 0.0;
+  opt->warm_iters = 0;
+  opt->warm_tau = 1e-3f;
   return DECONV_OK;
 }
 
@@ -533,6 +549,8 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   p->goff = at<long long>(w, lay.off_goff);
   p->hoff = at<long long>(w, lay.off_hoff);
   p->hsum = at<float2>(w, lay.off_hsum);
+  p->mu_cur = at<float>(w, lay.off_mu);
+  p->dscale = at<float>(w, lay.off_dscale);
   if (p->opt.ckpt_every > 0) {
     p->ck_yt = at<float>(w, lay.off_ck_yt);
     p->ck_v = at<float2>(w, lay.off_ck_v);
@@ -875,29 +893,79 @@ static IterFlags flags_for(const deconv_plan_s* p, int it, int iters) {
   return f;
 }
 
-// one iteration: column pass then row pass (+ residual reduction)
+// penalty the kernels read: the caller's, or the plan's adaptive copy
+static const float* mu_in_use(const deconv_plan_s* p, const float* mu) {
+  return p->opt.adapt_t > 0 ? p->mu_cur : mu;
+}
+
+// swaps of the double-buffered d per iteration (one more for the rescaling
+// pass of the adaptive penalty)
+static int d_swaps_per_iter(const deconv_plan_s* p) { return p->opt.adapt_t > 0 ? 2 : 1; }
+
+// One iteration: bgs_passes - 1 inner passes (column pass, then the row pass
+// that redoes the z-step and transforms ytilde again), the last column pass
+// and the row pass that finishes the iteration (+ residual reduction).  With
+// the adaptive penalty the row pass stops after the dual update, the residual
+// kernel updates mu and the factor of d (eq. (varying_penalty)), and a
+// ROW_STATE pass starts the next x-step from the rescaled state.
 static deconv_status launch_iteration(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
                                       IterFlags f, float* x_out, float2* u_out, float4* spec_store,
                                       int iters_since) {
-  ColArgs ca = col_args(p, mu);
+  const bool adapt = p->opt.adapt_t > 0;
+  const float* muk = mu_in_use(p, mu);
+  for (int q = 1; q < p->opt.bgs_passes; ++q) {
+    STCHK(launch_cols(p, col_args(p, muk)));
+    RowArgs ra = row_args(p, mask, lam, muk);
+    ra.mode = ROW_INNER;
+    STCHK(launch_rows(p, ra));
+  }
+  ColArgs ca = col_args(p, muk);
   ca.spec_store = spec_store;
   STCHK(launch_cols(p, ca));
-  RowArgs ra = row_args(p, mask, lam, mu);
+  RowArgs ra = row_args(p, mask, lam, muk);
   ra.mode = ROW_ITER;
   ra.d_in = p->dbuf[p->cur_d];
   ra.d_out = p->dbuf[1 - p->cur_d];
-  ra.check = f.check;
-  ra.store_v = f.store_v;
+  ra.check = f.check || adapt;
+  ra.store_v = f.store_v || adapt;
   ra.store_x = f.store_x;
-  ra.last = f.last;
+  ra.last = f.last || adapt;
   ra.x_out = x_out;
   ra.u_out = u_out;
   STCHK(launch_rows(p, ra));
   p->cur_d = 1 - p->cur_d;
-  if (f.check) {
+  if (f.check || adapt) {
     hipLaunchKernelGGL(residual_kernel, dim3(p->batch), dim3(kNT), 0, p->ls, p->d_meta, p->partials, p->res,
-                       p->done, p->nonfinite, p->iters_done, iters_since, p->opt.tol_primal, p->opt.tol_dual);
+                       p->done, p->nonfinite, p->iters_done, adapt ? 1 : iters_since, f.check,
+                       p->opt.tol_primal, p->opt.tol_dual, p->opt.adapt_t, p->mu_cur, p->dscale);
     HIPCHK(hipGetLastError());
+  }
+  if (adapt) {
+    RowArgs rs = row_args(p, mask, lam, p->mu_cur);
+    rs.mode = ROW_STATE;
+    rs.d_in = p->dbuf[p->cur_d];
+    rs.d_out = p->dbuf[1 - p->cur_d];
+    rs.dscale = p->dscale;
+    STCHK(launch_rows(p, rs));
+    p->cur_d = 1 - p->cur_d;
+  }
+  return DECONV_OK;
+}
+
+// Quadratic warm start of z (eqs. (ini_x), (ini_z)): each step solves
+// x = (H^T H + tau I)^{-1} H^T ytilde in the column pass and sets z = M_z H x
+// in an inner row pass (z-step without over-relaxation).  Starts from the
+// spectra of the initial state; v and d are untouched.
+static deconv_status warm_start(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu) {
+  for (int w = 0; w < p->opt.warm_iters; ++w) {
+    ColArgs ca = col_args(p, mu);
+    ca.warm = 1;
+    ca.warm_tau = p->opt.warm_tau;
+    STCHK(launch_cols(p, ca));
+    RowArgs ra = row_args(p, mask, lam, mu);
+    ra.mode = ROW_INNER;
+    ra.alpha = 1.f;
+    STCHK(launch_rows(p, ra));
   }
   return DECONV_OK;
 }
@@ -960,7 +1028,7 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
         g = p->graphs.emplace(key, exec).first;
       }
       HIPCHK(hipGraphLaunch(g->second, s));
-      if (K % 2) p->cur_d = 1 - cur0;
+      if ((K * d_swaps_per_iter(p)) % 2) p->cur_d = 1 - cur0;
       it += K;
       if (stopping) {
         std::vector<int> dn(p->batch);
@@ -990,7 +1058,8 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
   return DECONV_OK;
 }
 
-static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deconv_stats* stats) {
+static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deconv_stats* stats,
+                            const float* mu) {
   hipStream_t s = p->stream;
   if (ytilde_out)
     HIPCHK(hipMemcpyAsync(ytilde_out, p->yt, sizeof(float) * p->total_px, hipMemcpyDeviceToDevice, s));
@@ -998,6 +1067,8 @@ static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deco
     const int B = p->batch;
     std::vector<int> dn(B), itd(B), nf(B);
     std::vector<double> res(3 * B);
+    std::vector<float> muh(B);
+    HIPCHK(hipMemcpyAsync(muh.data(), mu, sizeof(float) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(itd.data(), p->iters_done, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(nf.data(), p->nonfinite, sizeof(int) * B, hipMemcpyDeviceToHost, s));
@@ -1010,6 +1081,7 @@ static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deco
       stats[b].r_dual = res[3 * b + 1];
       stats[b].r_z = res[3 * b + 2];
       stats[b].status = nf[b] ? DECONV_ERR_NONFINITE : DECONV_OK;
+      stats[b].mu = muh[b];
       if (nf[b]) ret = DECONV_ERR_NONFINITE;
     }
     return ret;
@@ -1053,12 +1125,15 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   hipLaunchKernelGGL(init_state_kernel, dim3(256, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean,
                      kMeanBlocks, p->yt, p->v, p->dbuf[0]);
   HIPCHK(hipGetLastError());
-  STCHK(prologue_from_state(p, mu));
+  if (p->opt.adapt_t > 0)
+    HIPCHK(hipMemcpyAsync(p->mu_cur, mu, sizeof(float) * p->batch, hipMemcpyDeviceToDevice, s));
+  STCHK(prologue_from_state(p, mu_in_use(p, mu)));
+  if (p->opt.warm_iters > 0) STCHK(warm_start(p, mask, lambda, mu));
   STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
   p->have_state = true;
   p->last_iters = iters;
   p->ck_valid = ckpt;
-  return finish(p, iters, ytilde_out, stats);
+  return finish(p, iters, ytilde_out, stats, mu_in_use(p, mu));
 }
 
 extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const float* mu, int32_t iters,
@@ -1068,9 +1143,11 @@ extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda
   if (needs_mask(p) && !p->mask) return DECONV_ERR_STATE;
   p->ck_valid = false;
   STCHK(reset_counters(p));
-  STCHK(prologue_from_state(p, mu));
+  if (p->opt.adapt_t > 0)
+    HIPCHK(hipMemcpyAsync(p->mu_cur, mu, sizeof(float) * p->batch, hipMemcpyDeviceToDevice, p->stream));
+  STCHK(prologue_from_state(p, mu_in_use(p, mu)));
   STCHK(iterate(p, p->mask, lambda, mu, iters, x_out, false));
-  return finish(p, iters, ytilde_out, stats);
+  return finish(p, iters, ytilde_out, stats, mu_in_use(p, mu));
 }
 
 extern "C" deconv_status deconv_state_export(deconv_plan p, float* ytilde, float* v, float* d) {

@@ -102,7 +102,11 @@ struct ImgMeta {
   long long rt0;       // first row-tile index of the image (residual partials)
 };
 
-enum { ROW_ITER = 0, ROW_STATE = 1 };
+// ROW_ITER: finish an iteration (z-step, prox, dual update) and start the
+// next x-step.  ROW_STATE: start an x-step from a stored state.  ROW_INNER:
+// one more block-Gauss-Seidel pass with v, d frozen (z-step on the own rows,
+// new transform of ytilde only; the mu G half of the spectra is kept).
+enum { ROW_ITER = 0, ROW_STATE = 1, ROW_INNER = 2 };
 
 struct RowArgs {
   const ImgMeta* meta;
@@ -121,6 +125,7 @@ struct RowArgs {
   const float2* tw;          // twiddle tables
   double* partials;          // 3 doubles per row tile (when check)
   const int* done;           // per-image stop flags, nullable
+  const float* dscale;       // ROW_STATE: per-image factor applied to d, nullable
   float alpha;
   int mode, check, store_v, store_x, last;
 };
@@ -136,6 +141,8 @@ struct ColArgs {
   const float2* tw;
   float4* spec_store;        // (Y, X) per frequency for the backward, nullable
   const int* done;
+  int warm;                  // 1: quadratic warm-start solve (|H|^2 + warm_tau)
+  float warm_tau;
 };
 
 // x % s == 0 for 0 <= x < 2^11 and 1 < s <= 2^11, with magic = floor(2^32/s) + 1
@@ -211,7 +218,7 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // Gather the tile's half spectra from the tiled layout into those lines,
 // completing the other half by Hermitian symmetry: X + iQ for the own rows,
 // X(r0-1) + i X(r0+nr) for the halo line.  All loads are issued first.
-template <int L, int RT>
+template <int L, int RT, bool HALO = true>
 __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC) {
   constexpr int LS = lstride(L);
@@ -241,7 +248,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   for (int k = 0; k < NH; ++k) {
     const int q = threadIdx.x + k * kNTR;
     const int c = q & (C - 1), blk = q >> logC;
-    if (blk < nb && blk * C + c < nh) {
+    if (HALO && blk < nb && blk * C + c < nh) {
       const unsigned base = __umul24(blk, M);
       ha[k] = sin2[2 * (((base + ia) << logC) + c)];
       hb[k] = sin2[2 * (((base + ib) << logC) + c)];
@@ -263,7 +270,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
     const int q = threadIdx.x + k * kNTR;
     const int c = q & (C - 1), blk = q >> logC;
     const int kx = blk * C + c;
-    if (blk < nb && kx < nh) {
+    if (HALO && blk < nb && kx < nh) {
       hline[lpad(kx)] = make_float2(ha[k].x - hb[k].y, ha[k].y + hb[k].x);
       if (kx >= 1 && kx <= L - nh) hline[lpad(L - kx)] = make_float2(ha[k].x + hb[k].y, hb[k].x - ha[k].y);
     }
@@ -365,6 +372,86 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
   split_store<L, RT>(sout, buf, M, r0, nr, nh, nb, C, logC);
 }
 
+// One more block-Gauss-Seidel pass of the x- and z-steps with v and d frozen
+// (the passes of Sec. III-B): the x-step's transform is finished on the own
+// rows only (no halo: the prox is not taken), the z-step updates ytilde, and
+// ytilde is transformed again, two real rows per complex line.  Only the Y
+// half of each spectrum entry is rewritten: the mu G half, a function of the
+// frozen v and d, is still valid.
+template <int L>
+__device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, int r0, float2* lds) {
+  using PM = PixMap<L>;
+  constexpr int RT = rt_for(L);
+  constexpr int LS = lstride(L);
+  constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;
+  constexpr int NBC_MAX = L / 2 + 16;
+  constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
+  const unsigned tid = threadIdx.x;
+  __builtin_assume(tid < (unsigned)kNTR);
+  const int M = mt.m;
+  const int nr = min(RT, M - r0);
+  const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
+  float* __restrict__ yt = a.yt + mt.px;
+  float2* buf = lds;
+  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
+  gather_rows<L, RT, false>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+  float yo[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l >= 1 && l <= nr) yo[k] = yt[(unsigned)((r0 + l - 1) * L + j)];
+  }
+  __syncthreads();
+  fft_lines<L, true, kNTR, RT>(buf, nr, tw);
+  // z-step on own row r = l - 1
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l >= 1 && l <= nr) {
+      const int i = r0 + l - 1;
+      const RowObs ro = row_observed(mt, i);
+      if (!pixel_observed(mt, ro, ro.explicit_mask ? a.mask + mt.px + i * L : nullptr, j)) {
+        const float hx = buf[(l - 1) * LS + lpad(j)].y;
+        yo[k] = yo[k] + a.alpha * (hx - yo[k]);
+        yt[(unsigned)(i * L + j)] = yo[k];
+      }
+    }
+  }
+  __syncthreads();
+  // rows 2q and 2q+1 into line q as a + i b (b = 0 past the last row)
+  float* bufs = reinterpret_cast<float*>(buf);
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l >= 1 && l <= nr) {
+      const int r = l - 1;
+      const int at = ((r >> 1) * LS + lpad(j)) * 2;
+      bufs[at + (r & 1)] = yo[k];
+      if (r + 1 == nr && !(r & 1)) bufs[at + 1] = 0.f;
+    }
+  }
+  __syncthreads();
+  const int npl = (nr + 1) >> 1;
+  fft_lines<L, false, kNTR, (RT + 1) / 2>(buf, npl, tw);
+  float2* __restrict__ sout2 = reinterpret_cast<float2*>(a.spec_out + mt.sp);
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = threadIdx.x + k * kNTR;
+    const int c = q & (C - 1);
+    const int t2 = q >> logC;
+    const int r = t2 % RT, blk = t2 / RT;
+    const int kx = blk * C + c;
+    if (r < nr && blk < nb && kx < nh) {
+      const float2* line = buf + (r >> 1) * LS;
+      const float2 cf = line[lpad(kx)];
+      const float2 cm = line[lpad(kx == 0 ? 0 : L - kx)];
+      const float2 y = (r & 1) ? make_float2(0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x))
+                               : make_float2(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y));
+      sout2[2 * (((__umul24(blk, M) + r0 + r) << logC) + c)] = y;
+    }
+  }
+}
+
 // Vector soft threshold factor: max(|u| - tau, 0) / |u| for |u|^2 = n2,
 // 0 when |u| <= tau (including u = 0).
 __device__ __forceinline__ float vsoft_scale(float n2, float tau, float tau2) {
@@ -383,6 +470,10 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   const unsigned tid = threadIdx.x;
   __builtin_assume(tid < (unsigned)kNTR);
   const ImgMeta mt = a.meta[img];
+  if (!PLAIN && a.mode == ROW_INNER) {
+    row_inner<L>(a, mt, r0, lds);
+    return;
+  }
   const int M = mt.m;
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
@@ -477,13 +568,16 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
       }
     }
   } else {
-    // ROW_STATE: start from a stored state (v, d, ytilde)
+    // ROW_STATE: start from a stored state (v, d, ytilde); d is rescaled by
+    // dscale (penalty update of eq. (varying_penalty))
+    const float ds = a.dscale ? a.dscale[img] : 1.f;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const int l = PM::row(k, tid), j = PM::col(k, tid);
       if (l <= nr) {
         const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
-        const float2 vv = vst[pix], dd = d_in[pix];
+        const float2 vv = vst[pix], d0 = d_in[pix];
+        const float2 dd = make_float2(ds * d0.x, ds * d0.y);
         wreg[k] = make_float2(vv.x - dd.x, vv.y - dd.y);
         if (l >= 1) {
           ynew[k] = yt[pix];
@@ -594,10 +688,13 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
       float2 X = make_float2(0.f, 0.f), Q = X;
       if (kx < mt.nh) {
         const float2 H = Hk[k];
-        const float den = H.x * H.x + H.y * H.y + mu * dsum[k];
+        const float h2 = H.x * H.x + H.y * H.y;
+        // x-step: (conj(H) Y + G) / (|H|^2 + mu |D|^2); warm start (eq. (ini_x)):
+        // conj(H) Y / (|H|^2 + tau)
+        const float2 Gk = a.warm ? make_float2(0.f, 0.f) : G;
+        const float den = a.warm ? h2 + a.warm_tau : h2 + mu * dsum[k];
         const float inv = scale * frcp(den);
-        // conj(H) Y + G
-        X = make_float2((H.x * Y.x + H.y * Y.y + G.x) * inv, (H.x * Y.y - H.y * Y.x + G.y) * inv);
+        X = make_float2((H.x * Y.x + H.y * Y.y + Gk.x) * inv, (H.x * Y.y - H.y * Y.x + Gk.y) * inv);
         Q = cmul(H, X);
         if (a.spec_store) a.spec_store[base + q] = make_float4(Y.x, Y.y, X.x, X.y);
       }

@@ -153,11 +153,15 @@ __global__ void __launch_bounds__(kNT) init_state_kernel(const ImgMeta* meta, co
 }
 
 // per image: FP64 sum of the row-tile partials -> |d'-d|, |v'-v|, |z'-z|;
-// optionally sets the stop flag
+// with stop_test, sets the stop flag when both tolerances hold; with
+// adapt_t > 0, the penalty update of eq. (varying_penalty): mu doubles (d
+// halves) when |d'-d| > t |v'-v|, mu halves (d doubles) when |v'-v| >
+// t |d'-d|; dscale receives the factor for d.
 __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, const double* partials,
                                                        double* res, int* done, int* nonfinite,
-                                                       int* iters_done, int iters_since,
-                                                       double tol_p, double tol_d) {
+                                                       int* iters_done, int iters_since, int stop_test,
+                                                       double tol_p, double tol_d, double adapt_t,
+                                                       float* mu_cur, float* dscale) {
   const int img = blockIdx.x;
   const ImgMeta mt = meta[img];
   double a = 0, b = 0, c = 0;
@@ -169,11 +173,21 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
   block_sum3(a, b, c, red);
   if (threadIdx.x == 0) {
     if (done && done[img]) return;
-    res[3 * img] = sqrt(a); res[3 * img + 1] = sqrt(b); res[3 * img + 2] = sqrt(c);
+    const double nd = sqrt(a), nv = sqrt(b);
+    res[3 * img] = nd; res[3 * img + 1] = nv; res[3 * img + 2] = sqrt(c);
     if (!isfinite(a) || !isfinite(b) || !isfinite(c)) nonfinite[img] = 1;
     iters_done[img] += iters_since;
     const double sc = sqrt(2.0 * (double)mt.m * (double)mt.n);
-    if (done && (tol_p > 0 || tol_d > 0) && sqrt(a) <= tol_p * sc && sqrt(b) <= tol_d * sc) done[img] = 1;
+    if (stop_test && done && (tol_p > 0 || tol_d > 0) && nd <= tol_p * sc && nv <= tol_d * sc) {
+      done[img] = 1;   // a stopped image keeps its penalty and its d
+      return;
+    }
+    if (adapt_t > 0) {
+      float f = 1.f;
+      if (nd > adapt_t * nv) { mu_cur[img] *= 2.f; f = 0.5f; }
+      else if (nv > adapt_t * nd) { mu_cur[img] *= 0.5f; f = 2.f; }
+      dscale[img] = f;
+    }
   }
 }
 

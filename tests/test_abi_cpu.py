@@ -50,7 +50,14 @@ def test_host_argument_checks():
            ([dict(height=64, width=64, ksize=5)], dict(alpha=2.5), 1),
            ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=0), 1),
            ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, tol_primal=1e-3), 1),
-           ([dict(height=4096, width=64, ksize=5)], {}, 2)]
+           ([dict(height=4096, width=64, ksize=5)], {}, 2),
+           ([dict(height=64, width=64, ksize=5)], dict(bgs_passes=0), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(adapt_t=-1.0), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(warm_iters=-1), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(warm_iters=10, warm_tau=0.0), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, bgs_passes=2), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, adapt_t=3.0), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, warm_iters=5), 1)]
     for images, opts, code in bad:
         with pytest.raises(binding.DeconvError) as e:
             binding.workspace_size(images, **opts)
@@ -59,3 +66,30 @@ def test_host_argument_checks():
     a = binding.workspace_size([dict(height=64, width=64, ksize=5)])
     b = binding.workspace_size([dict(height=64, width=64, ksize=5)], ckpt_every=5, max_iters=20)
     assert b > a
+
+
+def test_binding_struct_layout_matches_header(tmp_path):
+    """Sizes and field offsets of the option and statistics structs as the C
+    compiler lays them out, against the ctypes mirrors of the binding."""
+    import subprocess
+    from paper_1602_01410_amd import binding
+    src = tmp_path / "layout.c"
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "deconv.h"', 'int main(void) {']
+    for cname, cls in (("deconv_options", binding.Options), ("deconv_stats", binding.Stats),
+                       ("deconv_image_desc", binding.ImageDesc)):
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append('return 0; }')
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, cls in (("deconv_options", binding.Options), ("deconv_stats", binding.Stats),
+                       ("deconv_image_desc", binding.ImageDesc)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
