@@ -61,6 +61,9 @@ def _declare(L):
     L.or_admm_iterate.argtypes = [_I, _I, _I, _D, _U8, _F, _D, _F, _I, _I, _I, _F,
                                   _D, _D, _D, _D, _D, _D, _D]
     L.or_admm_iterate.restype = ctypes.c_double
+    L.or_admm_iterate_vec.argtypes = [_I, _I, _I, _I, _D, _U8, _F, _D, _F, _I, _I, _F,
+                                      _D, _D, _D, _D, _D, _D, _D]
+    L.or_admm_iterate_vec.restype = ctypes.c_double
     L.or_warm_start.argtypes = [_I, _I, _I, _D, _U8, _F, _I, _D]
     L.or_objective.argtypes = [_I, _I, _I, _D, _D, _D, _F, _I]
     L.or_objective.restype = ctypes.c_double
@@ -185,6 +188,33 @@ def admm_iterate(state, h, mask, lam, mu, iters, alpha=2.0, passes=1, phi="tv", 
                                *(state[k].ctypes.data_as(_D) for k in ("yt", "vh", "vv", "dh", "dv")),
                                x.ctypes.data_as(_D), hist.ctypes.data_as(_D))
     return x, hist[:iters], mu_c.value, mi
+
+
+def admm_run_vec(ys, masks, h, lam, mu, iters, alpha=2.0, passes=1, adapt_t=0.0, warm_iters=0,
+                 warm_tau=1e-3):
+    """Colour images with vectorial TV (Sec. III-C, demosaicing): ys, masks
+    (C, M, N); one blur h for all channels.  Each channel is initialised (and
+    warm-started) on its own; the iterations couple them in the v-step.
+    Returns a dict of (C, M, N) arrays x, yt, vh, vv, dh, dv and hist, mu."""
+    ys = np.asarray(ys, dtype=np.float64)
+    masks = np.ascontiguousarray(np.asarray(masks), dtype=np.uint8)
+    C, M, N = ys.shape
+    K = np.asarray(h).shape[0]
+    chans = [init_state(ys[c], masks[c], K) for c in range(C)]
+    if warm_iters:
+        for c in range(C):
+            warm_start(chans[c], h, masks[c], warm_tau, warm_iters)
+    st = {k: np.ascontiguousarray(np.stack([ch[k] for ch in chans])) for k in ("yt", "vh", "vv", "dh", "dv")}
+    hh, ph = _d(h)
+    x = np.zeros((C, M, N))
+    hist = np.zeros((max(iters, 1), 5))
+    mu_c = ctypes.c_double(mu)
+    mi = lib().or_admm_iterate_vec(M, N, K, C, ph, masks.ctypes.data_as(_U8), lam, ctypes.byref(mu_c), alpha,
+                                   passes, iters, adapt_t,
+                                   *(st[k].ctypes.data_as(_D) for k in ("yt", "vh", "vv", "dh", "dv")),
+                                   x.ctypes.data_as(_D), hist.ctypes.data_as(_D))
+    st.update(x=x, hist=hist[:iters], mu=mu_c.value, max_imag=mi)
+    return st
 
 
 def admm_run(y, mask, h, lam, mu, iters, alpha=2.0, passes=1, phi="tv", adapt_t=0.0,

@@ -537,6 +537,122 @@ double or_admm_iterate(int M, int N, int K, const double* h, const uint8_t* mask
     return max_imag;
 }
 
+/*
+ * Colour images (Sec. III-C, demosaicing): C channels x^1..x^C observed
+ * through the same blur, each with its own mask, data [y^j; z^j] and x-step.
+ * The data term is the sum of the per-channel terms, so the x- and z-steps
+ * are those of one channel, applied to each.  The regulariser is the
+ * vectorial TV, lambda times the per-pixel Euclidean norm of all 2C
+ * differences, so the v-step is one vector soft threshold over the 2C
+ * components of u = D x + d at each pixel.
+ * Arrays hold the channels one after the other (C * M * N values); v and d
+ * likewise per component (vh, vv, dh, dv each C * M * N).  Residuals and the
+ * penalty update use norms over all channels.  hist as or_admm_iterate.
+ * Parity: pinned by reduction to or_admm_iterate (C = 1, and lambda = 0 where
+ * the channels decouple) and by the identity that C equal channels behave as
+ * one channel with lambda / sqrt(C).
+ */
+double or_admm_iterate_vec(int M, int N, int K, int C, const double* h, const uint8_t* masks,
+                           double lam, double* mu_io, double alpha, int passes, int iters,
+                           double adapt_t, double* yt, double* vh, double* vv, double* dh,
+                           double* dv, double* x, double* hist)
+{
+    size_t n = (size_t)M * N;
+    double mu = *mu_io;
+    ctx_t c = {M, N, K, masks, NULL, NULL, mu};
+    c.Hs = (cplx*)malloc(sizeof(cplx) * n);
+    c.den = (double*)malloc(sizeof(double) * n);
+    psf_spectrum(M, N, K, h, c.Hs);
+    cplx* G = (cplx*)malloc(sizeof(cplx) * n);
+    cplx* Y = (cplx*)malloc(sizeof(cplx) * n);
+    cplx* X = (cplx*)malloc(sizeof(cplx) * n);
+    double* g = (double*)malloc(sizeof(double) * n);
+    double* wh = (double*)malloc(sizeof(double) * n);
+    double* wv = (double*)malloc(sizeof(double) * n);
+    double* q = (double*)malloc(sizeof(double) * n);
+    double* zold = (double*)malloc(sizeof(double) * n * C);
+    double max_imag = 0;
+    for (int it = 0; it < iters; ++it) {
+        c.mu = mu;
+        for (int ky = 0; ky < M; ++ky)
+            for (int kx = 0; kx < N; ++kx) {
+                size_t k = (size_t)ky * N + kx;
+                double h2 = creal(c.Hs[k]) * creal(c.Hs[k]) + cimag(c.Hs[k]) * cimag(c.Hs[k]);
+                c.den[k] = h2 + mu * dsq(M, N, ky, kx);
+            }
+        memcpy(zold, yt, sizeof(double) * n * C);
+        /* x- and z-steps, channel by channel */
+        for (int ch = 0; ch < C; ++ch) {
+            size_t o = (size_t)ch * n;
+            c.mask = masks + o;
+            for (size_t j = 0; j < n; ++j) { wh[j] = vh[o + j] - dh[o + j]; wv[j] = vv[o + j] - dv[o + j]; }
+            or_gradT(M, N, wh, wv, g);
+            for (size_t j = 0; j < n; ++j) G[j] = g[j];
+            dft2(M, N, G, -1);
+            for (int p = 0; p < passes; ++p) bgs_pass(&c, G, alpha, yt + o, x + o, q, Y, X, &max_imag);
+        }
+        /* joint v- and d-steps over the 2C components */
+        double rd = 0, rv = 0, rz = 0;
+        double tau = lam / mu;
+        for (int i = 0; i < M; ++i)
+            for (int jj = 0; jj < N; ++jj) {
+                size_t k = (size_t)i * N + jj;
+                size_t kr = (size_t)i * N + (jj + 1) % N, kd = (size_t)((i + 1) % M) * N + jj;
+                double nrm2 = 0;
+                for (int ch = 0; ch < C; ++ch) {
+                    size_t o = (size_t)ch * n;
+                    double uh = x[o + kr] - x[o + k] + dh[o + k];
+                    double uv = x[o + kd] - x[o + k] + dv[o + k];
+                    nrm2 += uh * uh + uv * uv;
+                }
+                double nrm = sqrt(nrm2);
+                double s = nrm > tau ? (nrm - tau) / nrm : 0.0;
+                for (int ch = 0; ch < C; ++ch) {
+                    size_t o = (size_t)ch * n;
+                    double uh = x[o + kr] - x[o + k] + dh[o + k];
+                    double uv = x[o + kd] - x[o + k] + dv[o + k];
+                    double nvh = s * uh, nvv = s * uv;
+                    double ndh = uh - nvh, ndv = uv - nvv;
+                    rd += (ndh - dh[o + k]) * (ndh - dh[o + k]) + (ndv - dv[o + k]) * (ndv - dv[o + k]);
+                    rv += (nvh - vh[o + k]) * (nvh - vh[o + k]) + (nvv - vv[o + k]) * (nvv - vv[o + k]);
+                    /* u reads d at this pixel only, so v and d update in place */
+                    vh[o + k] = nvh; vv[o + k] = nvv;
+                    dh[o + k] = ndh; dv[o + k] = ndv;
+                }
+            }
+        for (int ch = 0; ch < C; ++ch) {
+            size_t o = (size_t)ch * n;
+            for (int i = 0; i < M; ++i)
+                for (int jj = 0; jj < N; ++jj) {
+                    size_t k = (size_t)i * N + jj;
+                    if (!observed(M, N, K / 2, masks + o, i, jj))
+                        rz += (yt[o + k] - zold[o + k]) * (yt[o + k] - zold[o + k]);
+                }
+        }
+        if (hist) {
+            hist[5 * it + 0] = sqrt(rd);
+            hist[5 * it + 1] = sqrt(rv);
+            hist[5 * it + 2] = sqrt(rz);
+            hist[5 * it + 3] = rz + mu * rv + mu * rd;
+            hist[5 * it + 4] = mu;
+        }
+        if (adapt_t > 0) {
+            double nd = sqrt(rd), nv = sqrt(rv);
+            if (nd > adapt_t * nv) {
+                mu *= 2.0;
+                for (size_t j = 0; j < n * C; ++j) { dh[j] *= 0.5; dv[j] *= 0.5; }
+            } else if (nv > adapt_t * nd) {
+                mu *= 0.5;
+                for (size_t j = 0; j < n * C; ++j) { dh[j] *= 2.0; dv[j] *= 2.0; }
+            }
+        }
+    }
+    *mu_io = mu;
+    free(zold); free(q); free(wv); free(wh); free(g); free(X); free(Y); free(G);
+    free(c.den); free(c.Hs);
+    return max_imag;
+}
+
 /* Quadratic warm start for z (eqs. (ini_x), (ini_z)): `iters` alternations of
    x = (H^T H + tau I)^{-1} H^T [y; z],  z = M_z H x,  from yt in place. */
 void or_warm_start(int M, int N, int K, const double* h, const uint8_t* mask,

@@ -173,6 +173,59 @@ def problem(M, N, K, kind="rect", blur="box", sigma=None, mask_kind=MASK_BOUNDAR
                 K=K, M=M, N=N, mask_kind=mask_kind, decim=decim if mask_kind == MASK_DECIMATE else 1)
 
 
+def box_kernel_even(size):
+    """A size x size box (size even) on the odd (size+1)^2 support the method
+    needs: the box covers offsets -size/2 .. size/2-1 around the centre,
+    i.e. its anchor is the pixel (size/2, size/2) of the box."""
+    h = np.zeros((size + 1, size + 1))
+    h[:size, :size] = 1.0 / (size * size)
+    return h
+
+
+def bayer_masks(M, N, K):
+    """RGGB colour-filter masks (3, M, N) over the valid region, phase at its
+    top-left corner: red at (even, even) offsets, green at (even, odd) and
+    (odd, even), blue at (odd, odd); the band of width b is unobserved."""
+    b = K // 2
+    ii, jj = np.meshgrid(np.arange(M) - b, np.arange(N) - b, indexing="ij")
+    valid = make_mask(M, N, K).astype(bool)
+    red = (ii % 2 == 0) & (jj % 2 == 0)
+    blue = (ii % 2 == 1) & (jj % 2 == 1)
+    green = ~red & ~blue
+    return np.stack([red & valid, green & valid, blue & valid]).astype(np.uint8)
+
+
+def rgb_problem(M, N, K=9, seed=0, bsnr=40.0, lam=1e-5, mu=1e-3, nrect=16):
+    """Colour deblurring + demosaicing (Sec. III-C): rectangles with
+    per-channel intensities (edges shared by the channels) plus a ramp,
+    jointly normalised to [0, 1]; an 8x8 box blur on a 9x9 support (K = 9);
+    Bayer masks; noise at `bsnr` dB per channel over its observed pixels."""
+    rng = np.random.default_rng(seed)
+    x = np.zeros((3, M, N))
+    for _ in range(nrect):
+        r0, r1 = np.sort(rng.integers(0, M + 1, size=2))
+        c0, c1 = np.sort(rng.integers(0, N + 1, size=2))
+        x[:, r0:r1, c0:c1] = rng.uniform(0.0, 1.0, size=3)[:, None, None]
+    x += 0.2 * (np.arange(N)[None, None, :] / float(max(N - 8, 1))) * rng.uniform(0.5, 1.0, size=3)[:, None, None]
+    x = (x - x.min()) / (x.max() - x.min())
+    h = box_kernel_even(K - 1) if K % 2 == 1 else box_kernel_even(K)
+    K = h.shape[0]
+    masks = bayer_masks(M, N, K)
+    ys = np.stack([observe(x[c], h, masks[c], bsnr, rng) for c in range(3)])
+    return dict(x_true=f32(x), h=f32(h), masks=masks, ys=f32(ys), lam=float(lam), mu=float(mu), K=K, M=M, N=N)
+
+
+def config_demosaic(seed=BASE_SEED + 5):
+    """288 x 256 extended domain (valid 280 x 248, the size of the paper's
+    289 x 253 crop rounded to FFT-friendly lengths), 8x8 box, Bayer masks,
+    BSNR 40 dB, lambda 1e-5, mu 1e-3 adapted with t = 3, 4 BGS passes."""
+    p = rgb_problem(288, 256, 9, seed=seed, bsnr=40.0, lam=1e-5, mu=1e-3)
+    p["iters"] = 200
+    p["passes"] = 4
+    p["adapt_t"] = 3.0
+    return p
+
+
 def config_plain_72(seed=BASE_SEED + 0):
     """72x72 extended domain, 12 rectangles + ramp 0.2*col/64, 9x9 box blur,
     observed central 64x64, BSNR 50 dB, lambda 1e-3, mu 0.05, 200 iterations."""
