@@ -55,7 +55,28 @@ def workload(name):
         ps = [synth.problem(1024, 1024, 19, "grf", "gauss", sigma=3.0, bsnr=50.0, lam=5e-4, mu=0.02,
                             seed=synth.BASE_SEED * 1000 + 500 + b) for b in range(16)]
         return ps, 500, "16x1024^2 GRF+rects, 19x19 Gaussian s=3, unknown boundaries, 500 it"
+    if name == "demosaic_288x256":
+        return colour_channels(synth.config_demosaic()), 200, \
+            "RGB 288x256 (valid 280x248), 8x8 box, Bayer masks, vectorial TV, 4 BGS passes, adaptive mu, 200 it"
     raise ValueError(name)
+
+
+def colour_channels(p):
+    """The channels of a colour problem as consecutive grey images of one
+    plan (opt.channels = 3)."""
+    from paper_1602_01410_amd import synth
+    out = []
+    for c in range(3):
+        out.append(dict(y=p["ys"][c], mask=p["masks"][c], h=p["h"], lam=p["lam"], mu=p["mu"], M=p["M"], N=p["N"],
+                        K=p["K"], mask_kind=synth.MASK_EXPLICIT, decim=1, colour=p))
+    return out
+
+
+def plan_options(name):
+    """Options of the method each workload runs with (beyond the defaults)."""
+    if name == "demosaic_288x256":
+        return dict(channels=3, bgs_passes=4, adapt_t=3.0)
+    return {}
 
 
 def descs(problems):
@@ -136,12 +157,26 @@ def time_runs(plan, inputs, iters, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def cpu_baseline(problems, target_s=15.0):
+def cpu_baseline(problems, target_s=15.0, opts=None):
     """The FP64 oracle on the host cores, on a bounded sample of the
     workload: the first image, as many iterations as fit in ~target_s."""
     import numpy as np
     import oracle
     p = problems[0]
+    if "colour" in p:
+        c = p["colour"]
+        args = (c["ys"].astype(np.float64), c["masks"], c["h"].astype(np.float64), float(c["lam"]), float(c["mu"]))
+        kw = dict(passes=opts.get("bgs_passes", 1), adapt_t=opts.get("adapt_t", 0.0))
+        t0 = time.perf_counter()
+        oracle.admm_run_vec(*args, 2, **kw)
+        t2 = time.perf_counter() - t0
+        n = int(max(2, min(200, target_s / max(t2 / 2.0, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.admm_run_vec(*args, n, **kw)
+        t = time.perf_counter() - t0
+        return dict(value=3 * c["M"] * c["N"] * n / t / 1e6, unit="Mpixel*ADMM-iters/s", cores=oracle.num_threads(),
+                    kind="oracle", sample="colour image (3x%dx%d), %d iterations incl. setup, %.1f s" %
+                    (c["M"], c["N"], n, t))
     args = (p["y"].astype(np.float64), p["mask"], p["h"].astype(np.float64), float(p["lam"]), float(p["mu"]))
     t0 = time.perf_counter()
     oracle.admm_run(*args, 2)
@@ -160,7 +195,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_1024",
-                    choices=["large_1024", "plain_72", "inpaint_2048", "batch_256", "uniform_16x1024"])
+                    choices=["large_1024", "plain_72", "inpaint_2048", "batch_256", "uniform_16x1024",
+                             "demosaic_288x256"])
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-compare", action="store_true")
@@ -196,7 +232,8 @@ def main():
     npx = sum(p["M"] * p["N"] for p in problems)
     unobs = unobserved_fraction(problems)
     inputs = to_device(problems)
-    plan = binding.Plan(descs(problems), batched=1, use_graph=1, check_every=args.check_every)
+    popts = plan_options(args.workload)
+    plan = binding.Plan(descs(problems), batched=1, use_graph=1, check_every=args.check_every, **popts)
     log("launch shapes (row, column; 1 = per length, 2 = one launch): %s" % (plan.schedule(),))
     log("timing %d steps (+%d warmup), %d images, %d px, %d iterations" % (args.steps, args.warmup,
                                                                           len(problems), npx, iters))
@@ -206,7 +243,8 @@ def main():
     log("value %.1f Mpx*it/s, %.3f ms/step (wall %.3f s)" % (value, ms_step, wall))
 
     roof = None
-    if not args.no_kernel_times:
+    # the byte model below is that of one pass per iteration (plain method)
+    if not args.no_kernel_times and not popts:
         # per-launch GPU time of each pass, HIP events on the plan's stream
         pplan = binding.Plan(descs(problems), batched=1, use_graph=0, check_every=args.check_every, profile=1)
         y, mask, h, lam, mu = inputs
@@ -256,7 +294,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
-        cpu = cpu_baseline(problems)
+        cpu = cpu_baseline(problems, opts=popts)
         cpu["value"] = round(cpu["value"], 4)
         log("  %s" % cpu)
 
@@ -265,7 +303,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": args.workload, "description": wdesc, "images": len(problems), "pixels": npx,
-                      "iters": iters, "check_every": args.check_every, "unobserved_fraction": round(unobs, 4)},
+                      "iters": iters, "check_every": args.check_every, "unobserved_fraction": round(unobs, 4),
+                      "options": popts},
            "roofline": roof, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out), flush=True)

@@ -116,6 +116,14 @@ typedef struct {
                            warm start of eqs. (ini_x), (ini_z) (Sec. III-B uses
                            100); 0 = edge replication only (default) */
   float warm_tau;       /* tau of the warm start (default 1e-3) */
+  int32_t channels;     /* C > 1: colour images with vectorial TV (Sec. III-C,
+                           demosaicing).  Images c*C .. c*C+C-1 of the batch are
+                           the channels of one colour image: same size and
+                           ksize, each with its own data, mask and blur; the
+                           prox is one soft threshold over the 2C differences
+                           of a pixel, with lambda and mu of the first channel
+                           (pass equal values).  C <= 4; no reverse pass.
+                           Default 1. */
 } deconv_options;
 
 typedef struct {

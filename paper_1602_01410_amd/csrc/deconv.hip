@@ -286,6 +286,15 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     // initial state
     if (opt->ckpt_every > 0 && (opt->bgs_passes != 1 || opt->adapt_t > 0 || opt->warm_iters > 0))
       return DECONV_ERR_INVALID_ARG;
+    // colour groups: consecutive images of one size; no reverse pass
+    if (opt->channels < 1 || opt->channels > kMaxChannels || batch % opt->channels != 0)
+      return DECONV_ERR_INVALID_ARG;
+    if (opt->channels > 1 && opt->ckpt_every > 0) return DECONV_ERR_INVALID_ARG;
+    for (int b = 0; b < batch; ++b) {
+      const deconv_image_desc& f = desc[b - b % opt->channels];
+      if (desc[b].height != f.height || desc[b].width != f.width || desc[b].ksize != f.ksize)
+        return DECONV_ERR_INVALID_ARG;
+    }
   }
   for (int b = 0; b < batch; ++b) {
     const deconv_image_desc& d = desc[b];
@@ -321,6 +330,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     m.rt = rt_for(d.width);
     m.nrt = (d.height + m.rt - 1) / m.rt;
     m.px = px; m.sp = sp; m.hh = hhp; m.tab = tab; m.rt0 = rt;
+    m.nch = std::max(1, p->opt.channels);
+    m.group = b - b % m.nch;
     for (int L : {d.width, d.height})
       if (!twoff.count(L)) { twoff[L] = tw; tw += L; }
     m.twr = twoff[d.width]; m.twc = twoff[d.height];
@@ -470,6 +481,7 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->adapt_t = 0.0;
   opt->warm_iters = 0;
   opt->warm_tau = 1e-3f;
+  opt->channels = 1;
   return DECONV_OK;
 }
 
@@ -900,7 +912,9 @@ static const float* mu_in_use(const deconv_plan_s* p, const float* mu) {
 
 // swaps of the double-buffered d per iteration (one more for the rescaling
 // pass of the adaptive penalty)
-static int d_swaps_per_iter(const deconv_plan_s* p) { return p->opt.adapt_t > 0 ? 2 : 1; }
+static int d_swaps_per_iter(const deconv_plan_s* p) {
+  return p->opt.adapt_t > 0 || p->opt.channels > 1 ? 2 : 1;
+}
 
 // One iteration: bgs_passes - 1 inner passes (column pass, then the row pass
 // that redoes the z-step and transforms ytilde again), the last column pass
@@ -922,30 +936,42 @@ static deconv_status launch_iteration(deconv_plan_s* p, const uint8_t* mask, con
   ColArgs ca = col_args(p, muk);
   ca.spec_store = spec_store;
   STCHK(launch_cols(p, ca));
+  const bool colour = p->opt.channels > 1;
+  const bool resid = f.check || adapt;
   RowArgs ra = row_args(p, mask, lam, muk);
-  ra.mode = ROW_ITER;
+  ra.mode = colour ? ROW_UONLY : ROW_ITER;
   ra.d_in = p->dbuf[p->cur_d];
   ra.d_out = p->dbuf[1 - p->cur_d];
-  ra.check = f.check || adapt;
+  ra.check = resid;
   ra.store_v = f.store_v || adapt;
   ra.store_x = f.store_x;
   ra.last = f.last || adapt;
   ra.x_out = x_out;
   ra.u_out = u_out;
   STCHK(launch_rows(p, ra));
+  if (colour) {
+    // joint prox of each colour group: u (in d_out) -> v, d^{i+1}
+    int ntile = 0;
+    for (auto& m : p->meta) ntile = std::max(ntile, m.nrt);
+    hipLaunchKernelGGL(group_prox_kernel, dim3(ntile, p->batch / p->opt.channels), dim3(kNT), 0, p->ls,
+                       p->d_meta, lam, muk, p->dbuf[p->cur_d], p->dbuf[1 - p->cur_d], p->v, p->partials,
+                       resid ? 1 : 0, p->done);
+    HIPCHK(hipGetLastError());
+  }
   p->cur_d = 1 - p->cur_d;
-  if (f.check || adapt) {
+  if (resid) {
     hipLaunchKernelGGL(residual_kernel, dim3(p->batch), dim3(kNT), 0, p->ls, p->d_meta, p->partials, p->res,
                        p->done, p->nonfinite, p->iters_done, adapt ? 1 : iters_since, f.check,
                        p->opt.tol_primal, p->opt.tol_dual, p->opt.adapt_t, p->mu_cur, p->dscale);
     HIPCHK(hipGetLastError());
   }
-  if (adapt) {
-    RowArgs rs = row_args(p, mask, lam, p->mu_cur);
+  if (adapt || colour) {
+    // next x-step from the stored state (d rescaled by the penalty update)
+    RowArgs rs = row_args(p, mask, lam, muk);
     rs.mode = ROW_STATE;
     rs.d_in = p->dbuf[p->cur_d];
     rs.d_out = p->dbuf[1 - p->cur_d];
-    rs.dscale = p->dscale;
+    rs.dscale = adapt ? p->dscale : nullptr;
     STCHK(launch_rows(p, rs));
     p->cur_d = 1 - p->cur_d;
   }

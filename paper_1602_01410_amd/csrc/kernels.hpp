@@ -100,13 +100,17 @@ struct ImgMeta {
   long long tab;       // offset in the |D|^2 tables (float)
   long long twr, twc;  // twiddle table offsets for lengths n' and m'
   long long rt0;       // first row-tile index of the image (residual partials)
+  int group;           // first image of the colour group (itself for grey images)
+  int nch;             // channels of the group (1 for grey images)
 };
 
 // ROW_ITER: finish an iteration (z-step, prox, dual update) and start the
 // next x-step.  ROW_STATE: start an x-step from a stored state.  ROW_INNER:
 // one more block-Gauss-Seidel pass with v, d frozen (z-step on the own rows,
 // new transform of ytilde only; the mu G half of the spectra is kept).
-enum { ROW_ITER = 0, ROW_STATE = 1, ROW_INNER = 2 };
+// ROW_UONLY: colour images; the z-step and u = D x + d of the own rows (into
+// d_out), the joint prox of the channels following in its own kernel.
+enum { ROW_ITER = 0, ROW_STATE = 1, ROW_INNER = 2, ROW_UONLY = 3 };
 
 struct RowArgs {
   const ImgMeta* meta;
@@ -478,6 +482,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   const bool check = !PLAIN && a.check;
+  const bool uonly = !PLAIN && a.mode == ROW_UONLY;
   const bool store_v = !PLAIN && a.store_v;
   const bool store_x = !PLAIN && a.store_x;
   // image-local bases (uniform) with 32-bit offsets below
@@ -497,7 +502,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   float2 wreg[KP];
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
-  if (PLAIN || a.mode == ROW_ITER) {
+  if (PLAIN || a.mode == ROW_ITER || uonly) {
     gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
     __syncthreads();
 #if DCV_EARLY_STATE
@@ -546,13 +551,13 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
         const float dh = uh - vh, dv = uv - vv;
         wreg[k] = make_float2(vh - dh, vv - dv);
         if (l >= 1) {
-          d_out[pix] = make_float2(dh, dv);
-          if (check) {
+          d_out[pix] = uonly ? make_float2(uh, uv) : make_float2(dh, dv);
+          if (check && !uonly) {
             rd += (dh - dd[k].x) * (dh - dd[k].x) + (dv - dd[k].y) * (dv - dd[k].y);
             const float2 vo = vst[pix];
             rv += (vh - vo.x) * (vh - vo.x) + (vv - vo.y) * (vv - vo.y);
           }
-          if (store_v) vst[pix] = make_float2(vh, vv);
+          if (store_v && !uonly) vst[pix] = make_float2(vh, vv);
           float yn = yo[k];
           const RowObs ro = row_observed(mt, i);
           if (!pixel_observed(mt, ro, ro.explicit_mask ? a.mask + mt.px + i * L : nullptr, j)) {
@@ -596,7 +601,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
       out[0] = rdd; out[1] = rvd; out[2] = rzd;
     }
   }
-  if (!PLAIN && a.last) return;
+  if (!PLAIN && (a.last || uonly)) return;
   // prologue of the next x-step: pack ytilde + i mu D^T(v - d)
   row_prologue<L, RT, KP>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
                           [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); });

@@ -157,6 +157,9 @@ __global__ void __launch_bounds__(kNT) init_state_kernel(const ImgMeta* meta, co
 // adapt_t > 0, the penalty update of eq. (varying_penalty): mu doubles (d
 // halves) when |d'-d| > t |v'-v|, mu halves (d doubles) when |v'-v| >
 // t |d'-d|; dscale receives the factor for d.
+// For a colour group |d'-d| and |v'-v| run over all its channels (the joint
+// prox leaves them in the partials of the group's first image), so every
+// channel takes the same stop and penalty decisions.
 __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, const double* partials,
                                                        double* res, int* done, int* nonfinite,
                                                        int* iters_done, int iters_since, int stop_test,
@@ -164,11 +167,13 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
                                                        float* mu_cur, float* dscale) {
   const int img = blockIdx.x;
   const ImgMeta mt = meta[img];
+  const ImgMeta mg = meta[mt.group];
   double a = 0, b = 0, c = 0;
-  for (int t = threadIdx.x; t < mt.nrt; t += kNT) {
-    const double* p = partials + 3 * (mt.rt0 + t);
-    a += p[0]; b += p[1]; c += p[2];
+  for (int t = threadIdx.x; t < mg.nrt; t += kNT) {
+    const double* p = partials + 3 * (mg.rt0 + t);
+    a += p[0]; b += p[1];
   }
+  for (int t = threadIdx.x; t < mt.nrt; t += kNT) c += partials[3 * (mt.rt0 + t) + 2];
   __shared__ double red[3 * (kNT / 64)];
   block_sum3(a, b, c, red);
   if (threadIdx.x == 0) {
@@ -187,6 +192,65 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
       if (nd > adapt_t * nv) { mu_cur[img] *= 2.f; f = 0.5f; }
       else if (nv > adapt_t * nd) { mu_cur[img] *= 0.5f; f = 2.f; }
       dscale[img] = f;
+    }
+  }
+}
+
+// Joint prox of a colour group (vectorial TV of Sec. III-C): at each pixel one
+// vector soft threshold over the 2C components u^c = D x^c + d^c of the
+// group's C channels, whose images follow each other in the packed arrays.
+// u arrives in d_new (ROW_UONLY pass); d_new and v receive d^{i+1}, v^{i+1}.
+// One block per row tile of the group's first image; with check, |d'-d|^2
+// and |v'-v|^2 of the tile go to its partials.  tau = lambda / mu of the
+// first channel.
+constexpr int kMaxChannels = 4;
+__global__ void __launch_bounds__(kNT) group_prox_kernel(const ImgMeta* meta, const float* lam, const float* mu,
+                                                         const float2* __restrict__ d_old, float2* d_new, float2* v,
+                                                         double* partials, int check, const int* done) {
+  const int g0 = blockIdx.y * meta[0].nch;
+  const ImgMeta mt = meta[g0];
+  if (done && done[g0]) return;
+  const int t = blockIdx.x;
+  if (t >= mt.nrt) return;
+  const float tau = lam[g0] / mu[g0];
+  const float tau2 = tau * tau;
+  const int r0 = t * mt.rt, nr = min(mt.rt, mt.m - r0);
+  const long long plane = (long long)mt.m * mt.n;
+  const int npx = nr * mt.n;
+  float rd = 0.f, rv = 0.f;
+  for (int p = threadIdx.x; p < npx; p += kNT) {
+    const long long pix = mt.px + (long long)r0 * mt.n + p;
+    float2 u[kMaxChannels];
+    float n2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < kMaxChannels; ++c)
+      if (c < mt.nch) {
+        u[c] = d_new[pix + c * plane];
+        n2 += u[c].x * u[c].x + u[c].y * u[c].y;
+      }
+    const float s = vsoft_scale(n2, tau, tau2);
+#pragma unroll
+    for (int c = 0; c < kMaxChannels; ++c)
+      if (c < mt.nch) {
+        const long long q = pix + c * plane;
+        const float2 vn = make_float2(s * u[c].x, s * u[c].y);
+        const float2 dn = make_float2(u[c].x - vn.x, u[c].y - vn.y);
+        if (check) {
+          const float2 d0 = d_old[q], v0 = v[q];
+          rd += (dn.x - d0.x) * (dn.x - d0.x) + (dn.y - d0.y) * (dn.y - d0.y);
+          rv += (vn.x - v0.x) * (vn.x - v0.x) + (vn.y - v0.y) * (vn.y - v0.y);
+        }
+        v[q] = vn;
+        d_new[q] = dn;
+      }
+  }
+  if (check) {
+    __shared__ double red[3 * (kNT / 64)];
+    double a = rd, b = rv, z = 0.0;
+    block_sum3(a, b, z, red);
+    if (threadIdx.x == 0) {
+      partials[3 * (mt.rt0 + t)] = a;
+      partials[3 * (mt.rt0 + t) + 1] = b;
     }
   }
 }

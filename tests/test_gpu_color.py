@@ -1,0 +1,91 @@
+"""Colour images with vectorial TV (Sec. III-C, deblurring + demosaicing) on
+the HIP path against the FP64 oracle: channels are consecutive images of a
+plan with opt.channels = 3, Bayer masks, one joint prox per pixel."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_01410_amd import synth
+
+from .gpu_util import assert_parity, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_colour(probs, iters, **opts):
+    import torch
+    from paper_1602_01410_amd import binding
+    descs, ys, ms, hs, lams, mus = [], [], [], [], [], []
+    for p in probs:
+        for c in range(3):
+            descs.append(dict(height=p["M"], width=p["N"], ksize=p["K"], mask_kind=binding.MASK_EXPLICIT))
+            ys.append(p["ys"][c].ravel())
+            ms.append(p["masks"][c].ravel())
+            hs.append(p["h"].ravel())
+            lams.append(p["lam"])
+            mus.append(p["mu"])
+    plan = binding.Plan(descs, channels=3, **opts)
+    y = torch.from_numpy(np.concatenate(ys).astype(np.float32)).cuda()
+    mask = torch.from_numpy(np.concatenate(ms).astype(np.uint8)).cuda()
+    h = torch.from_numpy(np.concatenate(hs).astype(np.float32)).cuda()
+    lam = torch.tensor(lams, dtype=torch.float32).cuda()
+    mu = torch.tensor(mus, dtype=torch.float32).cuda()
+    yt = torch.empty_like(y)
+    x, st = plan.run(y, mask, h, lam, mu, iters, ytilde_out=yt, stats=True)
+    torch.cuda.synchronize()
+    xs = [a.cpu().numpy().astype(np.float64) for a in plan.split(x)]
+    yts = [a.cpu().numpy().astype(np.float64) for a in plan.split(yt)]
+    return xs, yts, st
+
+
+def _oracle_colour(p, iters, **kw):
+    return oracle.admm_run_vec(p["ys"].astype(np.float64), p["masks"], p["h"].astype(np.float64),
+                               float(np.float32(p["lam"])), float(np.float32(p["mu"])), iters, **kw)
+
+
+def _check(p, xs, yts, st, r, base, what, yt_rel=1e-4):
+    for c in range(3):
+        assert_parity(xs[base + c], r["x"][c], what="%s ch%d x" % (what, c))
+        assert_parity(yts[base + c], r["yt"][c], rel=yt_rel, what="%s ch%d ytilde" % (what, c))
+        assert st[base + c]["mu"] == pytest.approx(r["mu"], rel=1e-6)
+
+
+def test_colour_small_fixed_penalty():
+    p = synth.rgb_problem(48, 64, 9, seed=61, bsnr=40.0, lam=2e-3, mu=0.05)
+    xs, yts, st = _gpu_colour([p], 60)
+    _check(p, xs, yts, st, _oracle_colour(p, 60), 0, "48x64")
+
+
+def test_colour_two_sizes_passes_adaptive_warm_graph():
+    """Two colour images of different sizes in one plan; 2 BGS passes, the
+    adaptive penalty, 30 warm-start steps, graph replay of check periods."""
+    probs = [synth.rgb_problem(48, 64, 9, seed=62, bsnr=40.0, lam=1e-3, mu=0.5),
+             synth.rgb_problem(72, 96, 9, seed=63, bsnr=35.0, lam=2e-3, mu=0.01)]
+    kw = dict(bgs_passes=2, adapt_t=3.0, warm_iters=30, warm_tau=1e-3)
+    xs, yts, st = _gpu_colour(probs, 40, check_every=10, use_graph=1, **kw)
+    for g, p in enumerate(probs):
+        r = _oracle_colour(p, 40, passes=2, adapt_t=3.0, warm_iters=30, warm_tau=1e-3)
+        log("image %d: mu GPU %.4g oracle %.4g" % (g, st[3 * g]["mu"], r["mu"]))
+        _check(p, xs, yts, st, r, 3 * g, "img%d" % g)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("alpha", [2.0, 1.0])
+def test_demosaic_workload_full_size(alpha):
+    """The demosaicing workload as bench.py runs it: 288 x 256, 8x8 box,
+    Bayer masks, 4 BGS passes, adaptive penalty, 200 iterations.
+
+    x is held to the 1e-4 bar.  With alpha = 2 the z-step is a reflection
+    (z <- 2 Hx - z on 3/4 of each channel's pixels) that does not damp
+    rounding: the FP32 ytilde drifts from the FP64 one linearly in the
+    number of z-steps, about 3.5e-7 relative per step on this workload
+    (P x iterations = 800 steps here), while with alpha = 1 it stays near
+    1e-5.  ytilde is therefore held to 1e-4 with alpha = 1 and to 5e-4
+    (800 x 3.5e-7 = 2.8e-4 with margin) with alpha = 2."""
+    p = synth.config_demosaic()
+    xs, yts, st = _gpu_colour([p], p["iters"], bgs_passes=p["passes"], adapt_t=p["adapt_t"], alpha=alpha,
+                              check_every=10, use_graph=1)
+    log("oracle (FP64), 288x256x3, %d iterations" % p["iters"])
+    r = _oracle_colour(p, p["iters"], passes=p["passes"], adapt_t=p["adapt_t"], alpha=alpha)
+    log("mu GPU %.4g oracle %.4g" % (st[0]["mu"], r["mu"]))
+    _check(p, xs, yts, st, r, 0, "demosaic", yt_rel=5e-4 if alpha == 2.0 else 1e-4)
