@@ -206,6 +206,7 @@ struct deconv_plan_s {
   int* done = nullptr;
   int* nonfinite = nullptr;
   int* iters_done = nullptr;
+  int* stop_buf = nullptr;    // d buffer holding a stopped image's last d
   double* res = nullptr;
   double* mean = nullptr;     // per image and row block: observed sum, count
   long long* goff = nullptr;
@@ -262,7 +263,7 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
-      off_part, off_done, off_nonf, off_itd, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
+      off_part, off_done, off_nonf, off_itd, off_stopbuf, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
       off_dscale;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
       off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64;
@@ -428,6 +429,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   lay.off_done = take(sizeof(int) * B);
   lay.off_nonf = take(sizeof(int) * B);
   lay.off_itd = take(sizeof(int) * B);
+  lay.off_stopbuf = take(sizeof(int) * B);
   lay.off_res = take(sizeof(double) * 3 * B);
   lay.off_mean = take(sizeof(double) * 2 * kMeanBlocks * B);
   lay.off_goff = take(sizeof(long long) * B);
@@ -556,6 +558,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   p->done = at<int>(w, lay.off_done);
   p->nonfinite = at<int>(w, lay.off_nonf);
   p->iters_done = at<int>(w, lay.off_itd);
+  p->stop_buf = at<int>(w, lay.off_stopbuf);
   p->res = at<double>(w, lay.off_res);
   p->mean = at<double>(w, lay.off_mean);
   p->goff = at<long long>(w, lay.off_goff);
@@ -900,7 +903,9 @@ static IterFlags flags_for(const deconv_plan_s* p, int it, int iters) {
   IterFlags f{};
   f.last = it == iters - 1;
   f.check = K > 0 && ((it + 1) % K == 0);
-  f.store_v = f.last || (K > 0 && (K == 1 || ((it + 2) % K == 0)));
+  // v is kept for the next check (it reads v^i) and at every check, so that
+  // an image stopped there leaves a consistent state (v, d of that iteration)
+  f.store_v = f.last || f.check || (K > 0 && (K == 1 || ((it + 2) % K == 0)));
   f.store_x = f.last || f.check;
   return f;
 }
@@ -962,7 +967,8 @@ static deconv_status launch_iteration(deconv_plan_s* p, const uint8_t* mask, con
   if (resid) {
     hipLaunchKernelGGL(residual_kernel, dim3(p->batch), dim3(kNT), 0, p->ls, p->d_meta, p->partials, p->res,
                        p->done, p->nonfinite, p->iters_done, adapt ? 1 : iters_since, f.check,
-                       p->opt.tol_primal, p->opt.tol_dual, p->opt.adapt_t, p->mu_cur, p->dscale);
+                       p->opt.tol_primal, p->opt.tol_dual, p->opt.adapt_t, p->mu_cur, p->dscale, p->stop_buf,
+                       p->cur_d);
     HIPCHK(hipGetLastError());
   }
   if (adapt || colour) {
@@ -1079,8 +1085,13 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
       if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
     }
   }
-  // an early stop skipped the final store of x and v for the images that had
-  // already converged: they stored x at their converging check iteration.
+  // Images that stopped early kept x, v and d of their stopping iteration;
+  // their d sits in the buffer current then.  Bring it to the current one.
+  if (stopping) {
+    hipLaunchKernelGGL(stopped_d_kernel, dim3(64, p->batch), dim3(kNT), 0, s, p->d_meta, p->done, p->stop_buf,
+                       p->cur_d, p->dbuf[0], p->dbuf[1]);
+    HIPCHK(hipGetLastError());
+  }
   return DECONV_OK;
 }
 

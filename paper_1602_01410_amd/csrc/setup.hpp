@@ -164,7 +164,8 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
                                                        double* res, int* done, int* nonfinite,
                                                        int* iters_done, int iters_since, int stop_test,
                                                        double tol_p, double tol_d, double adapt_t,
-                                                       float* mu_cur, float* dscale) {
+                                                       float* mu_cur, float* dscale, int* stop_buf,
+                                                       int cur_d) {
   const int img = blockIdx.x;
   const ImgMeta mt = meta[img];
   const ImgMeta mg = meta[mt.group];
@@ -184,7 +185,8 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
     iters_done[img] += iters_since;
     const double sc = sqrt(2.0 * (double)mt.m * (double)mt.n);
     if (stop_test && done && (tol_p > 0 || tol_d > 0) && nd <= tol_p * sc && nv <= tol_d * sc) {
-      done[img] = 1;   // a stopped image keeps its penalty and its d
+      done[img] = 1;   // a stopped image keeps its penalty and its d (in buffer cur_d)
+      stop_buf[img] = cur_d;
       return;
     }
     if (adapt_t > 0) {
@@ -194,6 +196,19 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
       dscale[img] = f;
     }
   }
+}
+
+// After a run with early stopping: copy the d of each stopped image from the
+// buffer it stopped in to the current one (no-op for the others).
+__global__ void __launch_bounds__(kNT) stopped_d_kernel(const ImgMeta* meta, const int* done, const int* stop_buf,
+                                                        int cur_d, float2* d0, float2* d1) {
+  const int img = blockIdx.y;
+  if (!done[img] || stop_buf[img] == cur_d) return;
+  const ImgMeta mt = meta[img];
+  const float2* src = (cur_d == 0 ? d1 : d0) + mt.px;
+  float2* dst = (cur_d == 0 ? d0 : d1) + mt.px;
+  const long long n = (long long)mt.m * mt.n;
+  for (long long i = (long long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long long)gridDim.x * kNT) dst[i] = src[i];
 }
 
 // Joint prox of a colour group (vectorial TV of Sec. III-C): at each pixel one

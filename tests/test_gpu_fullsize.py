@@ -134,7 +134,8 @@ def test_early_stop_on_residuals():
     probs = [synth.problem(64, 64, 5, "rect", "box", bsnr=50.0, lam=1e-2, mu=0.2, seed=90),
              synth.problem(96, 72, 7, "rect", "gauss", sigma=1.5, bsnr=40.0, lam=2e-3, mu=0.01, seed=91)]
     iters, K = 300, 10
-    g = gpu_run(probs, iters, batched=1, use_graph=1, check_every=K, tol_primal=2e-4, tol_dual=2e-4)
+    g = gpu_run(probs, iters, want_state=True, batched=1, use_graph=1, check_every=K, tol_primal=2e-4,
+                tol_dual=2e-4)
     stopped = 0
     for b, p in enumerate(probs):
         st = g["stats"][b]
@@ -145,6 +146,13 @@ def test_early_stop_on_residuals():
         assert_parity(g["x"][b], r["x"], what="img%d x at its stop" % b)
         if n < iters:
             stopped += 1
+            # the state left behind is that of the stopping iteration
+            sh = (p["M"], p["N"], 2)
+            assert_parity(g["yt"][b], r["yt"], what="img%d ytilde at its stop" % b)
+            assert_parity(g["v"][b].reshape(sh), np.stack([r["vh"], r["vv"]], -1), rel=1e-3, absfrac=1e-2,
+                          what="img%d v at its stop" % b)
+            assert_parity(g["d"][b].reshape(sh), np.stack([r["dh"], r["dv"]], -1), rel=1e-3, absfrac=1e-2,
+                          what="img%d d at its stop" % b)
             sc = np.sqrt(2.0 * p["M"] * p["N"])
             assert st["r_primal"] <= 2e-4 * sc and st["r_dual"] <= 2e-4 * sc
             h = r["hist"][-1]
