@@ -123,6 +123,7 @@ struct Group {
   long long tile0;
   int ntiles;
   size_t lds;
+  int rt;   // row pass: rows per tile (0 = rt_for(L))
 };
 
 // A tile of a pass: image, first row (row pass) or column block (column
@@ -310,9 +311,45 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
   return DECONV_OK;
 }
 
+static int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, v = 0;
+    n = (hipGetDevice(&dev) == hipSuccess &&
+         hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            ? v
+            : 256;
+  }
+  return n;
+}
+
+static bool has_half_rt(int L) {
+  switch (L) {
+#define DCV_CASE(n) case n: return true;
+    DCV_FOR_EACH_HALF_RT_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return false;
+}
+
+// A plan whose images share one width and that has fewer row tiles than two
+// per compute unit (one 1024^2 image: 256) takes tiles of half the rows:
+// twice the workgroups, each with a shorter chain of dependent steps.  Not
+// with checkpoints: the reverse pass uses the default tiles.
+static bool use_half_rt(const deconv_plan_s* p) {
+  std::set<int> ws;
+  long long tiles = 0;
+  for (auto& d : p->desc) {
+    ws.insert(d.width);
+    tiles += (d.height + rt_for(d.width) - 1) / rt_for(d.width);
+  }
+  return ws.size() == 1 && has_half_rt(*ws.begin()) && tiles < 2 * num_cus() && p->opt.ckpt_every == 0;
+}
+
 // build per-image metadata and the workspace layout
 static void build_layout(deconv_plan_s* p, Layout& lay) {
   const int B = p->batch;
+  const bool half = use_half_rt(p);
   p->meta.assign(B, ImgMeta{});
   p->hoff_h.assign(B, 0);
   long long px = 0, sp = 0, hhp = 0, tab = 0, rt = 0, hk = 0;
@@ -328,7 +365,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     m.C = c_for(d.height);
     m.logC = 0; while ((1 << m.logC) < m.C) ++m.logC;
     m.nb = (m.nh + m.C - 1) / m.C;
-    m.rt = rt_for(d.width);
+    m.rt = half ? rt_half(d.width) : rt_for(d.width);
     m.nrt = (d.height + m.rt - 1) / m.rt;
     m.px = px; m.sp = sp; m.hh = hhp; m.tab = tab; m.rt0 = rt;
     m.nch = std::max(1, p->opt.channels);
@@ -367,15 +404,17 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     for (int t = 0; t < m.nb; ++t) ct_tiles[b].push_back(TileRef{b, t, (double)m.C * m.m * lc});
   }
   size_t rlds = 0, clds = 0;
-  for (int w : widths) rlds = std::max(rlds, row_lds_bytes(w));
+  const int grt = half ? rt_half(*widths.begin()) : 0;
+  for (int w : widths) rlds = std::max(rlds, row_lds_bytes(w, grt));
   for (int h : heights) clds = std::max(clds, col_lds_bytes(h));
-  auto add_group = [&](std::vector<Group>& dst, int L, size_t lds, const std::vector<std::vector<TileRef>>& imgs) {
+  auto add_group = [&](std::vector<Group>& dst, int L, size_t lds, const std::vector<std::vector<TileRef>>& imgs,
+                       int rt) {
     const long long t0 = (long long)p->h_tiles.size();
     xcd_schedule(imgs, p->h_tiles);
-    dst.push_back(Group{L, t0, (int)((long long)p->h_tiles.size() - t0), lds});
+    dst.push_back(Group{L, t0, (int)((long long)p->h_tiles.size() - t0), lds, rt});
   };
-  add_group(p->row_sets[1], widths.size() == 1 ? *widths.begin() : 0, rlds, rt_tiles);
-  add_group(p->col_sets[1], heights.size() == 1 ? *heights.begin() : 0, clds, ct_tiles);
+  add_group(p->row_sets[1], widths.size() == 1 ? *widths.begin() : 0, rlds, rt_tiles, grt);
+  add_group(p->col_sets[1], heights.size() == 1 ? *heights.begin() : 0, clds, ct_tiles, 0);
   if (widths.size() == 1) {
     p->row_sets[0] = p->row_sets[1];
   } else {
@@ -383,7 +422,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
       std::vector<std::vector<TileRef>> sel(B);
       for (int b = 0; b < B; ++b)
         if (p->meta[b].n == w) sel[b] = rt_tiles[b];
-      add_group(p->row_sets[0], w, row_lds_bytes(w), sel);
+      add_group(p->row_sets[0], w, row_lds_bytes(w), sel, 0);
     }
   }
   if (heights.size() == 1) {
@@ -393,7 +432,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
       std::vector<std::vector<TileRef>> sel(B);
       for (int b = 0; b < B; ++b)
         if (p->meta[b].m == h) sel[b] = ct_tiles[b];
-      add_group(p->col_sets[0], h, col_lds_bytes(h), sel);
+      add_group(p->col_sets[0], h, col_lds_bytes(h), sel, 0);
     }
   }
   const int rs = p->opt.schedule == 1 ? 0 : 1, cs = p->opt.schedule == 1 ? 0 : 1;
@@ -404,10 +443,10 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   for (int b = 0; b < B; ++b) {
     std::vector<std::vector<TileRef>> one(B);
     one[b] = rt_tiles[b];
-    add_group(p->row_img[b], p->meta[b].n, row_lds_bytes(p->meta[b].n), one);
+    add_group(p->row_img[b], p->meta[b].n, row_lds_bytes(p->meta[b].n, grt), one, grt);
     one[b].clear();
     one[b] = ct_tiles[b];
-    add_group(p->col_img[b], p->meta[b].m, col_lds_bytes(p->meta[b].m), one);
+    add_group(p->col_img[b], p->meta[b].m, col_lds_bytes(p->meta[b].m), one, 0);
   }
   const long long ntiles = (long long)p->h_tiles.size();
 
@@ -745,7 +784,8 @@ static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
   const std::vector<Group>& gs = p->opt.batched ? p->row_groups : pass_groups(p, true);
   for (size_t k = 0; k < gs.size(); ++k) {
     a.tiles = p->d_tiles + gs[k].tile0;
-    HIPCHK(launch_row(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size())));
+    HIPCHK(launch_row(gs[k].L, gs[k].rt, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k),
+                      timer.stop(k, gs.size())));
   }
   timer.done();
   return DECONV_OK;

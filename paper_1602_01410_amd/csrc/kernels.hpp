@@ -72,7 +72,13 @@ constexpr int kTwLds = DCV_TW_GLOBAL ? 0 : 1;
 #ifndef DCV_EARLY_STATE
 #define DCV_EARLY_STATE 1
 #endif
-__host__ __device__ constexpr int row_lds_elems(int L) { return (rt_for(L) + 1) * lstride(L) + kTwLds * L; }
+__host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
+  return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLds * L;
+}
+// Lengths that also have row tiles of half the rows (rt_for(L) / 2), for
+// plans with too few tiles to fill the chip
+#define DCV_FOR_EACH_HALF_RT_LEN(X) X(512) X(1024) X(2048)
+__host__ __device__ constexpr int rt_half(int L) { return rt_for(L) / 2 > 0 ? rt_for(L) / 2 : 1; }
 __host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLds * L; }
 
 // the twiddle table a workgroup uses for length L (caller synchronises)
@@ -382,10 +388,9 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
 // ytilde is transformed again, two real rows per complex line.  Only the Y
 // half of each spectrum entry is rewritten: the mu G half, a function of the
 // frozen v and d, is still valid.
-template <int L>
+template <int L, int RT>
 __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, int r0, float2* lds) {
   using PM = PixMap<L>;
-  constexpr int RT = rt_for(L);
   constexpr int LS = lstride(L);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;
   constexpr int NBC_MAX = L / 2 + 16;
@@ -465,17 +470,16 @@ __device__ __forceinline__ float vsoft_scale(float n2, float tau, float tau2) {
 // PLAIN: an iteration that neither checks residuals nor stores v, x or u
 // (most iterations between two residual checks); the flags are then
 // compile-time constants.
-template <int L, bool PLAIN>
+template <int L, bool PLAIN, int RT = rt_for(L)>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
   using PM = PixMap<L>;
-  constexpr int RT = rt_for(L);
   constexpr int LS = lstride(L);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;  // pixels per thread (own rows + 1 halo)
   const unsigned tid = threadIdx.x;
   __builtin_assume(tid < (unsigned)kNTR);
   const ImgMeta mt = a.meta[img];
   if (!PLAIN && a.mode == ROW_INNER) {
-    row_inner<L>(a, mt, r0, lds);
+    row_inner<L, RT>(a, mt, r0, lds);
     return;
   }
   const int M = mt.m;
@@ -612,12 +616,12 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
 #ifndef DCV_ROW_WAVES
 #define DCV_ROW_WAVES 1
 #endif
-template <int L, bool PLAIN>
+template <int L, bool PLAIN, int RT = rt_for(L)>
 __global__ void __launch_bounds__(kNTR, DCV_ROW_WAVES) row_kernel(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  row_tile<L, PLAIN>(a, t.x, t.y, lds);
+  row_tile<L, PLAIN, RT>(a, t.x, t.y, lds);
 }
 
 // one launch for tiles of every line length: dispatch on the tile's length

@@ -42,11 +42,13 @@ inline hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void
 // L = 0 launches the kernel that dispatches on each tile's length.
 // launch_row picks the plain-iteration instantiation when the arguments ask
 // for no residuals and no stores of v, x or u.
-size_t row_lds_bytes(int L);
+size_t row_lds_bytes(int L, int rt = 0);
 size_t col_lds_bytes(int L);
-hipError_t launch_row(int L, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0 = nullptr,
+// rt: rows per tile of the group (0 or rt_for(L): the default; rt_half(L) for
+// the lengths of DCV_FOR_EACH_HALF_RT_LEN)
+hipError_t launch_row(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
-hipError_t launch_row_plain(int L, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
+hipError_t launch_row_plain(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
                             hipEvent_t e1);
 hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);

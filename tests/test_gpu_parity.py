@@ -74,6 +74,26 @@ def _small(M, N, K, kind=synth.MASK_BOUNDARY, seed=0, decim=3, missing=0.3, blur
                          lam=lam, mu=mu, seed=seed, nrect=6)
 
 
+@pytest.mark.parametrize("shape", [(512, 512, synth.MASK_EXPLICIT), (256, 2048, synth.MASK_DECIMATE),
+                                   (1024, 1024, synth.MASK_BOUNDARY)])
+def test_half_height_row_tiles(torch_cuda, shape):
+    """Plans of one width with few row tiles use tiles of half the rows (a
+    512^2 image: 4-row tiles, 256 x 2048: 1-row tiles, 1024^2: 2-row tiles);
+    results agree with the oracle, with the check/store iterations, graphs
+    and one BGS-pass variant exercising every row-pass mode."""
+    M, N, kind = shape
+    p = _small(M, N, 9, kind, seed=M + N, blur="gauss", lam=3e-3)
+    iters = 30
+    g = gpu_run([p], iters, check_every=10, use_graph=1)
+    r = oracle_run(p, iters)
+    assert_parity(g["x"][0], r["x"], what="%dx%d x" % (M, N))
+    assert_parity(g["yt"][0], r["yt"], what="%dx%d ytilde" % (M, N))
+    g2 = gpu_run([p], 12, bgs_passes=2, adapt_t=3.0)
+    r2 = oracle.admm_run(p["y"].astype(np.float64), p["mask"].astype(np.uint8), p["h"].astype(np.float64),
+                         float(np.float32(p["lam"])), float(np.float32(p["mu"])), 12, passes=2, adapt_t=3.0)
+    assert_parity(g2["x"][0], r2["x"], what="%dx%d x, 2 passes + adaptive" % (M, N))
+
+
 def test_one_iteration_full_state(torch_cuda):
     """x^1, ytilde^1, v^1, d^1 after one iteration, per image of a mixed batch."""
     probs = [_small(24, 32, 5, synth.MASK_EXPLICIT, seed=1), _small(48, 36, 7, synth.MASK_DECIMATE, seed=2),
