@@ -257,12 +257,13 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
   }
   __syncthreads();
   fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
-  float4* __restrict__ sout = a.spec_out + base;
+  float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rt);
+  const unsigned nbc = (unsigned)(mt.nb * C);
   for (int q = threadIdx.x; q < L * C; q += kNTC) {
     const int i = q / C, c = q - i * C;
     const float2 X = buf[(2 * c) * LS + lpad(i)];
     const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-    sout[q] = make_float4(X.x, X.y, Q.x, Q.y);
+    sout[row_block_index(mt, i, nbc) + c * mt.rt] = make_float4(X.x, X.y, Q.x, Q.y);
   }
 }
 

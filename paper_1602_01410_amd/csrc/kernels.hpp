@@ -106,6 +106,7 @@ struct ImgMeta {
   long long tab;       // offset in the |D|^2 tables (float)
   long long twr, twc;  // twiddle table offsets for lengths n' and m'
   long long rt0;       // first row-tile index of the image (residual partials)
+  unsigned rtmagic;    // floor(2^32 / rt) + 1 (rt > 1): exact i / rt for rows i < 2^11
   int group;           // first image of the colour group (itself for grey images)
   int nch;             // channels of the group (1 for grey images)
 };
@@ -159,6 +160,14 @@ struct ColArgs {
 __device__ __forceinline__ bool divisible(int x, int s, unsigned magic) {
   const unsigned q = __umulhi((unsigned)x, magic);
   return (unsigned)x == q * (unsigned)s;
+}
+
+// offset of entry (row i, column 0 of the block) in the row-block layout of
+// the spectra the column pass writes for the row pass (entry (i, kx) at
+// (i / rt) rt nbc + kx rt + i mod rt; the caller adds (kx - blk C) rt)
+__device__ __forceinline__ unsigned row_block_index(const ImgMeta& mt, int i, unsigned nbc) {
+  const unsigned i0 = mt.rt == 1 ? (unsigned)i : __umulhi((unsigned)i, mt.rtmagic) * (unsigned)mt.rt;
+  return i0 * nbc + (unsigned)(i - (int)i0);
 }
 
 __device__ __forceinline__ bool observed(const ImgMeta& mt, const uint8_t* __restrict__ mask,
@@ -225,9 +234,11 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // halo rows packed as one complex line, x(r0-1) + i x(r0+nr).  Only x is
 // needed on the halo rows, so both share one transform.
 //
-// Gather the tile's half spectra from the tiled layout into those lines,
-// completing the other half by Hermitian symmetry: X + iQ for the own rows,
-// X(r0-1) + i X(r0+nr) for the halo line.  All loads are issued first.
+// Gather the tile's half spectra into those lines, completing the other
+// half by Hermitian symmetry: X + iQ for the own rows, X(r0-1) + i X(r0+nr)
+// for the halo line.  The column pass leaves the spectra in row blocks of
+// RT rows (entry (i, kx) at (i / RT) RT nbc + kx RT + i mod RT, nbc = nb C):
+// the own rows are one contiguous block.  All loads are issued first.
 template <int L, int RT, bool HALO = true>
 __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC) {
@@ -238,30 +249,29 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   const float2* __restrict__ sin2 = reinterpret_cast<const float2*>(sin);
   float4 g[NQ];
   int dst[NQ];
+  float2 ha[NH], hb[NH];
+  const int ia = r0 == 0 ? M - 1 : r0 - 1;
+  const int ib = r0 + nr == M ? 0 : r0 + nr;
+  // the tile's block: entry (r0 + l, kx) at r0 nbc + kx RT + l
+  const unsigned nbc = (unsigned)(nb * C);
+  const float4* __restrict__ blkp = sin + (unsigned)r0 * nbc;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = threadIdx.x + k * kNTR;
-    const int c = q & (C - 1);
-    const int t2 = q >> logC;
-    const int l = t2 % RT, blk = t2 / RT;
-    const int kx = blk * C + c;
+    const int l = q % RT, kx = q / RT;
     dst[k] = -1;
-    if (l < nr && blk < nb && kx < nh) {
-      g[k] = sin[((__umul24(blk, M) + r0 + l) << logC) + c];
+    if (l < nr && kx < nh) {
+      g[k] = blkp[q];
       dst[k] = l * LS + kx;
     }
   }
-  const int ia = r0 == 0 ? M - 1 : r0 - 1;
-  const int ib = r0 + nr == M ? 0 : r0 + nr;
-  float2 ha[NH], hb[NH];
+  const unsigned ba = (unsigned)(ia / RT) * RT * nbc + ia % RT, bb = (unsigned)(ib / RT) * RT * nbc + ib % RT;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const int q = threadIdx.x + k * kNTR;
-    const int c = q & (C - 1), blk = q >> logC;
-    if (HALO && blk < nb && blk * C + c < nh) {
-      const unsigned base = __umul24(blk, M);
-      ha[k] = sin2[2 * (((base + ia) << logC) + c)];
-      hb[k] = sin2[2 * (((base + ib) << logC) + c)];
+    const int kx = threadIdx.x + k * kNTR;
+    if (HALO && kx < nh) {
+      ha[k] = sin2[2 * (ba + (unsigned)kx * RT)];
+      hb[k] = sin2[2 * (bb + (unsigned)kx * RT)];
     }
   }
 #pragma unroll
@@ -277,10 +287,8 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   float2* hline = buf + nr * LS;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const int q = threadIdx.x + k * kNTR;
-    const int c = q & (C - 1), blk = q >> logC;
-    const int kx = blk * C + c;
-    if (HALO && blk < nb && kx < nh) {
+    const int kx = threadIdx.x + k * kNTR;
+    if (HALO && kx < nh) {
       hline[lpad(kx)] = make_float2(ha[k].x - hb[k].y, ha[k].y + hb[k].x);
       if (kx >= 1 && kx <= L - nh) hline[lpad(L - kx)] = make_float2(ha[k].x + hb[k].y, hb[k].x - ha[k].y);
     }
@@ -713,7 +721,9 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
   }
   __syncthreads();
   fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
-  float4* __restrict__ sout = a.spec_out + base;
+  // output in the row-block layout the row pass reads (runs of rt rows)
+  float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rt);
+  const unsigned nbc = (unsigned)(mt.nb * C);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = threadIdx.x + k * kNTC;
@@ -721,7 +731,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
       const int i = q / C, c = q - i * C;
       const float2 X = buf[(2 * c) * LS + lpad(i)];
       const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-      sout[q] = make_float4(X.x, X.y, Q.x, Q.y);
+      sout[row_block_index(mt, i, nbc) + c * mt.rt] = make_float4(X.x, X.y, Q.x, Q.y);
     }
   }
 }
