@@ -55,6 +55,10 @@ def workload(name):
         ps = [synth.problem(1024, 1024, 19, "grf", "gauss", sigma=3.0, bsnr=50.0, lam=5e-4, mu=0.02,
                             seed=synth.BASE_SEED * 1000 + 500 + b) for b in range(16)]
         return ps, 500, "16x1024^2 GRF+rects, 19x19 Gaussian s=3, unknown boundaries, 500 it"
+    if name == "grad_512":
+        ps = synth.config_grad_512()
+        return ps, ps[0]["iters"], \
+            "16x512^2 rects+ramp, 15x15 Gaussian s=2, unknown boundaries, 50 it forward + reverse (checkpoint every 10)"
     if name == "demosaic_288x256":
         return colour_channels(synth.config_demosaic()), 200, \
             "RGB 288x256 (valid 280x248), 8x8 box, Bayer masks, vectorial TV, 4 BGS passes, adaptive mu, 200 it"
@@ -76,6 +80,8 @@ def plan_options(name):
     """Options of the method each workload runs with (beyond the defaults)."""
     if name == "demosaic_288x256":
         return dict(channels=3, bgs_passes=4, adapt_t=3.0)
+    if name == "grad_512":
+        return dict(ckpt_every=10, max_iters=50)
     return {}
 
 
@@ -138,19 +144,31 @@ def read_traffic(name):
         return None, None
 
 
-def time_runs(plan, inputs, iters, steps, warmup):
+def time_runs(plan, inputs, iters, steps, warmup, backward=False):
+    """Seconds for `steps` runs (each: setup, init, all iterations; with
+    backward also the reverse pass for a fixed dL/dx), and the wall time."""
     import torch
     y, mask, h, lam, mu = inputs
     x = torch.empty(plan.npx, dtype=torch.float32, device="cuda")
-    for _ in range(warmup):
+    gx = None
+    if backward:
+        g = torch.Generator(device="cpu").manual_seed(7)
+        gx = (torch.randn(plan.npx, generator=g) / plan.npx).cuda()
+
+    def step():
         plan.run(y, mask, h, lam, mu, iters, x_out=x)
+        if backward:
+            plan.backward(y, mask, h, lam, mu, gx)
+
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     s = plan.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(s)
     for _ in range(steps):
-        plan.run(y, mask, h, lam, mu, iters, x_out=x)
+        step()
     e1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -178,15 +196,23 @@ def cpu_baseline(problems, target_s=15.0, opts=None):
                     kind="oracle", sample="colour image (3x%dx%d), %d iterations incl. setup, %.1f s" %
                     (c["M"], c["N"], n, t))
     args = (p["y"].astype(np.float64), p["mask"], p["h"].astype(np.float64), float(p["lam"]), float(p["mu"]))
+    if opts and opts.get("ckpt_every"):
+        # forward + reverse, as the GPU step
+        gx = np.random.default_rng(7).standard_normal((p["M"], p["N"])) / (p["M"] * p["N"])
+        run = lambda n: oracle.admm_backward(args[0], args[1].astype(np.uint8), args[2], args[3], args[4], n, gx)
+        what = "forward + reverse"
+    else:
+        run = lambda n: oracle.admm_run(*args, n)
+        what = "incl. setup"
     t0 = time.perf_counter()
-    oracle.admm_run(*args, 2)
+    run(2)
     t2 = time.perf_counter() - t0
     n = int(max(2, min(200, target_s / max(t2 / 2.0, 1e-6))))
     t0 = time.perf_counter()
-    oracle.admm_run(*args, n)
+    run(n)
     t = time.perf_counter() - t0
     return dict(value=p["M"] * p["N"] * n / t / 1e6, unit="Mpixel*ADMM-iters/s", cores=oracle.num_threads(),
-                kind="oracle", sample="image 0 (%dx%d), %d iterations incl. setup, %.1f s" % (p["M"], p["N"], n, t))
+                kind="oracle", sample="image 0 (%dx%d), %d iterations %s, %.1f s" % (p["M"], p["N"], n, what, t))
 
 
 def main():
@@ -196,7 +222,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_1024",
                     choices=["large_1024", "plain_72", "inpaint_2048", "batch_256", "uniform_16x1024",
-                             "demosaic_288x256"])
+                             "demosaic_288x256", "grad_512"])
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-compare", action="store_true")
@@ -237,10 +263,17 @@ def main():
     log("launch shapes (row, column; 1 = per length, 2 = one launch): %s" % (plan.schedule(),))
     log("timing %d steps (+%d warmup), %d images, %d px, %d iterations" % (args.steps, args.warmup,
                                                                           len(problems), npx, iters))
-    t, wall = time_runs(plan, inputs, iters, args.steps, args.warmup)
+    grad = args.workload == "grad_512"
+    t, wall = time_runs(plan, inputs, iters, args.steps, args.warmup, backward=grad)
     value = npx * iters * args.steps / t / 1e6
     ms_step = t / args.steps * 1e3
     log("value %.1f Mpx*it/s, %.3f ms/step (wall %.3f s)" % (value, ms_step, wall))
+    extra = {}
+    if grad:
+        tf, _ = time_runs(plan, inputs, iters, args.steps, 1)
+        extra["forward_only_ms_per_step"] = round(tf / args.steps * 1e3, 4)
+        extra["reverse_ms_per_step"] = round((t - tf) / args.steps * 1e3, 4)
+        log("forward %.3f ms, reverse %.3f ms per step" % (tf / args.steps * 1e3, (t - tf) / args.steps * 1e3))
 
     roof = None
     # the byte model below is that of one pass per iteration (plain method)
@@ -271,7 +304,6 @@ def main():
                                                   else rb / (row_avg * 1e-3)) / 1e9, 1)}}
         pplan.close()
 
-    extra = {}
     if args.workload == "large_1024" and not args.no_batch_compare:
         log("batched vs plain on the 256-image mixed batch")
         bp, bit, _ = workload("batch_256")

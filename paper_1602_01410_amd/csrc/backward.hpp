@@ -65,22 +65,35 @@ struct BwdColArgs {
 };
 
 // J^T t for the vector soft threshold at u (J is symmetric); also returns the
-// derivative of <S_tau(u), t> with respect to tau.
-__device__ __forceinline__ float2 vsoft_vjp(float2 u, float2 t, float tau, float& dtau) {
-  const float nr = sqrtf(u.x * u.x + u.y * u.y);
-  if (!(nr > tau)) { dtau = 0.f; return make_float2(0.f, 0.f); }
-  const float s = 1.f - tau / nr;
-  const float ut = (u.x * t.x + u.y * t.y);
-  const float c = ut * tau / (nr * nr * nr);
-  dtau = -ut / nr;
+// derivative of <S_tau(u), t> with respect to tau.  The active set is the one
+// of the forward shrink (|u|^2 > tau^2); with r = 1/|u|:
+// J^T t = (1 - tau r) t + tau r^3 <u, t> u,  d<S,t>/dtau = -r <u, t>.
+__device__ __forceinline__ float2 vsoft_vjp(float2 u, float2 t, float tau, float tau2, float& dtau) {
+  const float n2 = u.x * u.x + u.y * u.y;
+  if (!(n2 > tau2)) { dtau = 0.f; return make_float2(0.f, 0.f); }
+  const float r = __builtin_amdgcn_rsqf(n2);
+  const float ut = u.x * t.x + u.y * t.y;
+  const float s = 1.f - tau * r;
+  const float c = ut * tau * r * r * r;
+  dtau = -ut * r;
   return make_float2(s * t.x + c * u.x, s * t.y + c * u.y);
 }
 
+// reverse row pass: issue the epilogue's state loads before the inverse
+// transform (1: more registers) or after it (0)
+#ifndef DCV_BWD_EARLY_STATE
+#define DCV_BWD_EARLY_STATE 0
+#endif
+
 template <int L>
 __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r0, float2* lds) {
+  using PM = PixMap<L>;
   constexpr int RT = rt_for(L);
   constexpr int LS = lstride(L);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;
+  static_assert(KP <= 32, "observed flags of a thread's pixels are kept in one word");
+  const unsigned tid = threadIdx.x;
+  __builtin_assume(tid < (unsigned)kNTR);
   const ImgMeta mt = a.meta[img];
   const int M = mt.m;
   const int nr = min(RT, M - r0);
@@ -89,65 +102,105 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
-  const int npx = (nr + 1) * L;
+  const float tau2 = tau * tau;
+  const bool start = a.mode == BWD_START, end = a.mode == BWD_END;
+  float2* __restrict__ vb = a.vb + mt.px;
+  float2* __restrict__ db = a.db + mt.px;
+  float* __restrict__ zb = a.zb + mt.px;
+  float* __restrict__ yb = a.yb + mt.px;
+  const float2* __restrict__ ubin = start ? nullptr : a.ub_in + mt.px;
+  const float2* __restrict__ uin = end ? nullptr : a.u + mt.px;
+  float2* __restrict__ ubout = end ? nullptr : a.ub_out + mt.px;
   float2 ureg[KP];
   float qreg[KP];
   float lsum = 0.f;
 
-  if (a.mode != BWD_START) {
-    // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
+  // state loads of the epilogue, issued before the transform: ub (or vb, db
+  // at the start), u, and z-bar or y-bar of the own rows
+  float2 s0[KP], s1[KP], su[KP];
+  float sz[KP];
+  unsigned obsbits = 0;
+  if (!start) {
     gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+#if !DCV_BWD_EARLY_STATE
+    // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
+    __syncthreads();
+    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+#endif
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l <= nr) {
+      const int i = wrapi(r0 - 1 + l, M);
+      const unsigned pix = (unsigned)(i * L + j);
+      if (start) {
+        s0[k] = vb[pix];
+        s1[k] = db[pix];
+      } else {
+        s0[k] = ubin[pix];
+      }
+      if (!end) su[k] = uin[pix];
+      if (l >= 1) {
+        const RowObs ro = row_observed(mt, i);
+        const bool obs = pixel_observed(mt, ro, ro.explicit_mask ? a.mask + mt.px + i * L : nullptr, j);
+        obsbits |= (obs ? 1u : 0u) << k;
+        sz[k] = obs ? yb[pix] : zb[pix];
+      }
+    }
+  }
+#if DCV_BWD_EARLY_STATE
+  if (!start) {
+    // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
     __syncthreads();
     fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
   }
+#endif
 
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int p = threadIdx.x + k * kNTR;
-    if (p < npx) {
-      const int l = p / L, j = p - l * L;
+    const int l = PM::row(k, tid), j = PM::col(k, tid);
+    if (l <= nr) {
       const int i = wrapi(r0 - 1 + l, M);
-      const long long pix = mt.px + (long long)i * L + j;
+      const unsigned pix = (unsigned)(i * L + j);
       float2 vbv, dbv;
       float hr = 0.f;
-      if (a.mode == BWD_START) {
-        vbv = a.vb[pix];
-        dbv = a.db[pix];
+      if (start) {
+        vbv = s0[k];
+        dbv = s1[k];
       } else {
         const int lj = lpad(j);
         const float r = row_x<LS>(buf, l, nr, lj);
         if (l >= 1) hr = buf[(l - 1) * LS + lj].y;
         const float rr = row_x<LS>(buf, l, nr, lpad(j + 1 == L ? 0 : j + 1));
         const float rd = row_x<LS>(buf, l + 1, nr, lj);
-        const float2 ubo = a.ub_in[pix];
         vbv = make_float2(mu * (rr - r), mu * (rd - r));
-        dbv = make_float2(ubo.x - vbv.x, ubo.y - vbv.y);
+        dbv = make_float2(s0[k].x - vbv.x, s0[k].y - vbv.y);
       }
       float qb = 0.f;
       if (l >= 1) {
-        const bool obs = observed(mt, a.mask, i, j);
-        if (a.mode == BWD_START) {
-          if (!obs) qb = a.alpha * a.zb[pix];
+        const bool obs = (obsbits >> k) & 1u;
+        if (start) {
+          if (!obs) qb = a.alpha * sz[k];
         } else {
           if (obs) {
-            a.yb[pix] += hr;
+            yb[pix] = sz[k] + hr;
           } else {
-            const float zn = (1.f - a.alpha) * a.zb[pix] + hr;
-            a.zb[pix] = zn;
+            const float zn = (1.f - a.alpha) * sz[k] + hr;
+            zb[pix] = zn;
             qb = a.alpha * zn;
           }
-          if (a.mode == BWD_END) { a.vb[pix] = vbv; a.db[pix] = dbv; }
+          if (end) { vb[pix] = vbv; db[pix] = dbv; }
         }
       }
-      if (a.mode != BWD_END) {
-        const float2 uu = a.u[pix];
+      if (!end) {
         const float2 t = make_float2(vbv.x - dbv.x, vbv.y - dbv.y);
         float dt;
-        const float2 jt = vsoft_vjp(uu, t, tau, dt);
+        const float2 jt = vsoft_vjp(su[k], t, tau, tau2, dt);
         const float2 ub = make_float2(dbv.x + jt.x, dbv.y + jt.y);
         ureg[k] = ub;
         if (l >= 1) {
-          a.ub_out[pix] = ub;
+          ubout[pix] = ub;
           lsum += dt;
         }
       }
@@ -155,7 +208,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
     }
   }
 
-  if (a.mode != BWD_END) {
+  if (!end) {
     __shared__ double red[3 * (kNTR / 64)];
     double ls = lsum, z0 = 0.0, z1 = 0.0;
     block_sum3(ls, z0, z1, red);

@@ -66,61 +66,83 @@ __global__ void __launch_bounds__(kNT) init_adj_b_kernel(const ImgMeta* meta, co
 
 // observed pixels: + mean adjoint / count; unobserved: 0
 __global__ void __launch_bounds__(kNT) init_adj_c_kernel(const ImgMeta* meta, const uint8_t* __restrict__ mask,
-                                                         const double* mean_part, int nblk, const float* yb,
-                                                         float* grad_y) {
+                                                         const double* mean_part, int nblk, const double* obs_part,
+                                                         int nobs, const float* yb, float* grad_y) {
   const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
-  const long long n = (long long)mt.m * mt.n;
-  __shared__ double tot[2];
+  // the mean adjoint, spread over the observed pixels (their count comes
+  // from the forward run's observed-sum partials: sum, count per block)
+  __shared__ float add;
   if (threadIdx.x == 0) {
-    double s = 0;
+    double s = 0, c = 0;
     for (int k = 0; k < nblk; ++k) s += mean_part[(long long)img * nblk + k];
-    tot[0] = s;
+    for (int k = 0; k < nobs; ++k) c += obs_part[2 * ((long long)img * nobs + k) + 1];
+    add = c > 0 ? (float)(s / c) : 0.f;
   }
-  // count observed pixels
-  double cnt = 0;
-  for (long long p = threadIdx.x; p < n; p += kNT) {
-    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
-    if (observed(mt, mask, i, j)) cnt += 1.0;
-  }
-  __shared__ double red[3 * (kNT / 64)];
-  double z0 = 0, z1 = 0;
-  block_sum3(cnt, z0, z1, red);
-  if (threadIdx.x == 0) tot[1] = cnt;
   __syncthreads();
-  const float add = tot[1] > 0 ? (float)(tot[0] / tot[1]) : 0.f;
-  for (long long p = threadIdx.x; p < n; p += kNT) {
-    const int i = (int)(p / mt.n), j = (int)(p - (long long)i * mt.n);
-    grad_y[mt.px + p] = observed(mt, mask, i, j) ? yb[mt.px + p] + add : 0.f;
+  for (int i = blockIdx.x; i < mt.m; i += gridDim.x) {
+    const RowObs ro = row_observed(mt, i);
+    const uint8_t* mrow = ro.explicit_mask ? mask + mt.px + (long long)i * mt.n : nullptr;
+    for (int j = threadIdx.x; j < mt.n; j += kNT) {
+      const long long q = mt.px + (long long)i * mt.n + j;
+      grad_y[q] = pixel_observed(mt, ro, mrow, j) ? yb[q] + add : 0.f;
+    }
   }
 }
 
 // dL/dh[b+p][b+q] = (1/(m'n')) sum_k w(kx) Re(S_k exp(-2 pi i (ky p / m' + kx q / n')))
 // over the stored half spectrum (w = 1 for kx = 0 and kx = n'/2, 2 otherwise:
-// S is Hermitian).  FP64 throughout, with exact phase tables (index products
-// reduced modulo the length); one workgroup per (tap, image).
-__global__ void __launch_bounds__(kNT) grad_taps_kernel(const ImgMeta* meta, const double2* __restrict__ S,
-                                                       const double2* __restrict__ tw64, float* grad_h,
-                                                       const long long* hoff) {
+// S is Hermitian), in two separable stages: T[ky][q] = sum_kx w S_k
+// exp(-2 pi i kx q / n'), then sum_ky Re(T[ky][q] exp(-2 pi i ky p / m')).
+// FP64 throughout, with exact phase tables (index products reduced modulo
+// the length).  Stage 1: one thread per (ky, q); T has `tstride` entries per
+// image.
+__global__ void __launch_bounds__(kNT) grad_taps_rows_kernel(const ImgMeta* meta, const double2* __restrict__ S,
+                                                            const double2* __restrict__ tw64, double2* T,
+                                                            long long tstride) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const int K = 2 * mt.b + 1;
+  const int t = blockIdx.x * kNT + threadIdx.x;
+  if (t >= mt.m * K) return;
+  const int ky = t / K, qi = t - ky * K;
+  const int qq = qi - mt.b, qn = qq < 0 ? qq + mt.n : qq;
+  const double2* TN = tw64 + mt.twr;   // exp(-2 pi i k / n'), k < n'
+  double ar = 0.0, ai = 0.0;
+  int ph = 0;   // kx * qn mod n', stepped
+  for (int kx = 0; kx < mt.nh; ++kx) {
+    const double2 sv = S[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))];
+    const double2 e = TN[ph];
+    const double w = (kx == 0 || 2 * kx == mt.n) ? 1.0 : 2.0;
+    ar += w * (sv.x * e.x - sv.y * e.y);
+    ai += w * (sv.x * e.y + sv.y * e.x);
+    ph += qn;
+    if (ph >= mt.n) ph -= mt.n;
+  }
+  T[img * tstride + t] = make_double2(ar, ai);
+}
+
+// Stage 2: one workgroup per (tap, image), a sum over the m' rows.
+__global__ void __launch_bounds__(kNT) grad_taps_cols_kernel(const ImgMeta* meta, const double2* __restrict__ T,
+                                                            long long tstride, const double2* __restrict__ tw64,
+                                                            float* grad_h, const long long* hoff) {
   const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
   const int K = 2 * mt.b + 1;
   const int t = blockIdx.x;
   if (t >= K * K) return;
-  const int pp = t / K - mt.b, qq = t % K - mt.b;
-  const int pm = pp < 0 ? pp + mt.m : pp, qn = qq < 0 ? qq + mt.n : qq;
+  const int pi = t / K, qi = t % K;
+  const int pp = pi - mt.b, pm = pp < 0 ? pp + mt.m : pp;
   const double2* TM = tw64 + mt.twc;   // exp(-2 pi i k / m'), k < m'
-  const double2* TN = tw64 + mt.twr;   // exp(-2 pi i k / n'), k < n'
   double acc = 0.0;
-  const long long tot = (long long)mt.m * mt.nh;
-  for (long long q = threadIdx.x; q < tot; q += kNT) {
-    const int ky = (int)(q / mt.nh), kx = (int)(q - (long long)ky * mt.nh);
-    const double2 sv = S[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))];
-    const double2 a = TM[(int)(((long long)ky * pm) % mt.m)];
-    const double2 b = TN[(int)(((long long)kx * qn) % mt.n)];
-    const double er = a.x * b.x - a.y * b.y, ei = a.x * b.y + a.y * b.x;
-    const double w = (kx == 0 || 2 * kx == mt.n) ? 1.0 : 2.0;
-    acc += w * (sv.x * er - sv.y * ei);
+  int ph = (int)(((long long)threadIdx.x * pm) % mt.m);          // ky * pm mod m', stepped
+  const int step = (int)(((long long)kNT * pm) % mt.m);
+  for (int ky = threadIdx.x; ky < mt.m; ky += kNT) {
+    const double2 v = T[img * tstride + (long long)ky * K + qi];
+    const double2 e = TM[ph];
+    acc += v.x * e.x - v.y * e.y;
+    ph += step;
+    if (ph >= mt.m) ph -= mt.m;
   }
   __shared__ double red[3 * (kNT / 64)];
   double z0 = 0, z1 = 0;

@@ -229,6 +229,7 @@ struct deconv_plan_s {
   float* adj_z = nullptr;
   float* adj_y = nullptr;
   double2* adj_S = nullptr;   // accumulated spectral h-gradient (half, tiled, FP64)
+  double2* adj_T = nullptr;   // h-gradient: row-stage sums (max m' K per image, FP64)
   double2* tw64 = nullptr;    // FP64 twiddle tables (same offsets as tw), for the tap sums
   double* adj_lam = nullptr;  // per row tile partial of dL/dlambda
   int nck = 0;                // checkpoints stored
@@ -267,7 +268,7 @@ struct Layout {
       off_part, off_done, off_nonf, off_itd, off_stopbuf, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
       off_dscale;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
-      off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64;
+      off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64, off_adj_T;
   size_t total;
 };
 
@@ -496,10 +497,13 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     lay.off_adj_vb = take(sizeof(float2) * px);
     lay.off_adj_db = take(sizeof(float2) * px);
     lay.off_adj_mean = take(sizeof(double) * 64 * B);
+    long long mk = 1;
+    for (auto& d : p->desc) mk = std::max(mk, (long long)d.height * d.ksize);
+    lay.off_adj_T = take(sizeof(double2) * mk * B);
   } else {
     lay.off_ck_yt = lay.off_ck_v = lay.off_ck_d = lay.off_seg_u = lay.off_seg_spec = 0;
     lay.off_adj_a = lay.off_adj_b = lay.off_adj_z = lay.off_adj_y = lay.off_adj_S = lay.off_adj_lam = 0;
-    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = lay.off_tw64 = 0;
+    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = lay.off_tw64 = lay.off_adj_T = 0;
   }
   lay.total = o;
 }
@@ -618,6 +622,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
     p->adj_z = at<float>(w, lay.off_adj_z);
     p->adj_y = at<float>(w, lay.off_adj_y);
     p->adj_S = at<double2>(w, lay.off_adj_S);
+    p->adj_T = at<double2>(w, lay.off_adj_T);
     p->tw64 = at<double2>(w, lay.off_tw64);
     p->adj_lam = at<double>(w, lay.off_adj_lam);
     p->adj_vb = at<float2>(w, lay.off_adj_vb);
