@@ -102,7 +102,9 @@ typedef struct {
                            graph with HIP events (read by deconv_plan_kernel_times) */
   int32_t schedule;     /* batched launch shape of each pass: 0 = autotune at
                            plan creation (default), 1 = one launch per line
-                           length, 2 = one launch for all lengths */
+                           length, 2 = one launch for all lengths, 3 = one
+                           launch for the lengths with few tiles and one per
+                           other length */
   const char* tune_cache; /* nullable: file of autotuning decisions, read before
                            tuning and appended after (one line per batch
                            signature) */
@@ -227,8 +229,8 @@ deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* d
 deconv_status deconv_plan_kernel_times(deconv_plan p, double* out);
 
 /* Launch shapes in use (after autotuning): out[0] = row pass, out[1] =
-   column pass, each 1 (one launch per line length) or 2 (one launch for all
-   lengths).  Host call. */
+   column pass, each 1 (one launch per line length), 2 (one launch for all
+   lengths) or 3 (hybrid, see deconv_options.schedule).  Host call. */
 deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out);
 
 const char* deconv_status_str(deconv_status s);

@@ -240,7 +240,7 @@ struct deconv_plan_s {
   std::map<int, long long> tw_off;
   // batched launch shapes: [0] one group per line length, [1] one group for
   // all lengths; row_sched / col_sched pick one (autotuned)
-  std::vector<Group> row_sets[2], col_sets[2];
+  std::vector<Group> row_sets[3], col_sets[3];  // per length, one launch, hybrid
   int row_sched = 0, col_sched = 0;
   std::vector<Group> row_groups, col_groups;  // the chosen sets
   std::vector<int4> h_tiles;  // all tile tables, uploaded at plan creation
@@ -279,7 +279,7 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     if (opt->check_every < 0 || opt->ckpt_every < 0 || opt->max_iters < 0) return DECONV_ERR_INVALID_ARG;
     if (opt->tol_primal < 0 || opt->tol_dual < 0) return DECONV_ERR_INVALID_ARG;
     if (opt->ckpt_every > 0 && opt->max_iters <= 0) return DECONV_ERR_INVALID_ARG;
-    if (opt->schedule < 0 || opt->schedule > 2) return DECONV_ERR_INVALID_ARG;
+    if (opt->schedule < 0 || opt->schedule > 3) return DECONV_ERR_INVALID_ARG;
     // the reverse pass replays every iteration: no early stopping with it
     if (opt->ckpt_every > 0 && (opt->tol_primal > 0 || opt->tol_dual > 0)) return DECONV_ERR_INVALID_ARG;
     if (opt->bgs_passes < 1 || opt->bgs_passes > 64) return DECONV_ERR_INVALID_ARG;
@@ -391,7 +391,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   // and one per image for the per-image launches (batched = 0)
   p->h_tiles.clear();
   p->row_groups.clear(); p->col_groups.clear();
-  for (int k = 0; k < 2; ++k) { p->row_sets[k].clear(); p->col_sets[k].clear(); }
+  for (int k = 0; k < 3; ++k) { p->row_sets[k].clear(); p->col_sets[k].clear(); }
   p->row_img.assign(B, {}); p->col_img.assign(B, {});
   std::vector<std::vector<TileRef>> rt_tiles(B), ct_tiles(B);
   std::set<int> widths, heights;
@@ -438,7 +438,42 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
       add_group(p->col_sets[0], h, col_lds_bytes(h), sel, 0);
     }
   }
-  const int rs = p->opt.schedule == 1 ? 0 : 1, cs = p->opt.schedule == 1 ? 0 : 1;
+  // hybrid: the lengths whose tiles cannot fill the chip twice over (or that
+  // are short) share one launch, the others keep a launch each
+  auto hybrid = [&](bool rows) {
+    std::vector<Group>& dst = rows ? p->row_sets[2] : p->col_sets[2];
+    const std::set<int>& lens = rows ? widths : heights;
+    const auto& tiles = rows ? rt_tiles : ct_tiles;
+    std::map<int, long long> count;
+    for (int b = 0; b < B; ++b) count[rows ? p->meta[b].n : p->meta[b].m] += (long long)tiles[b].size();
+    std::set<int> small;
+    for (int L : lens)
+      if (L <= 256 || count[L] < 2LL * num_cus()) small.insert(L);
+    if (small.size() < 2 || small.size() == lens.size()) {
+      dst = small.size() == lens.size() ? (rows ? p->row_sets[1] : p->col_sets[1])
+                                        : (rows ? p->row_sets[0] : p->col_sets[0]);
+      return;
+    }
+    std::vector<std::vector<TileRef>> sel(B);
+    size_t lds = 0;
+    for (int b = 0; b < B; ++b) {
+      const int L = rows ? p->meta[b].n : p->meta[b].m;
+      if (small.count(L)) sel[b] = tiles[b];
+    }
+    for (int L : small) lds = std::max(lds, rows ? row_lds_bytes(L) : col_lds_bytes(L));
+    add_group(dst, 0, lds, sel, 0);
+    for (int L : lens) {
+      if (small.count(L)) continue;
+      std::vector<std::vector<TileRef>> one(B);
+      for (int b = 0; b < B; ++b)
+        if ((rows ? p->meta[b].n : p->meta[b].m) == L) one[b] = tiles[b];
+      add_group(dst, L, rows ? row_lds_bytes(L) : col_lds_bytes(L), one, 0);
+    }
+  };
+  hybrid(true);
+  hybrid(false);
+  // schedule 1, 2, 3 -> set 0, 1, 2; autotuning (0) starts from one launch
+  const int rs = p->opt.schedule >= 1 ? p->opt.schedule - 1 : 1, cs = rs;
   p->row_sched = rs;
   p->col_sched = cs;
   p->row_groups = p->row_sets[rs];
@@ -837,7 +872,7 @@ static bool cache_lookup(const char* path, const std::string& key, int* r, int* 
     const size_t t1 = line.find('\t');
     if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size()) continue;
     int rr = 0, cc = 0;
-    if (sscanf(line.c_str() + t1 + 1, "%d %d", &rr, &cc) == 2 && rr >= 0 && rr <= 1 && cc >= 0 && cc <= 1) {
+    if (sscanf(line.c_str() + t1 + 1, "%d %d", &rr, &cc) == 2 && rr >= 0 && rr <= 2 && cc >= 0 && cc <= 2) {
       *r = rr;
       *c = cc;
       found = true;   // the last entry wins
@@ -873,15 +908,15 @@ static deconv_status autotune(deconv_plan_s* p) {
     std::vector<float> hp(2 * p->batch, 0.f);
     for (int b = 0; b < p->batch; ++b) hp[p->batch + b] = 1.f;
     deconv_status st = DECONV_OK;
-    double best[2][2] = {{0, 0}, {0, 0}};
+    double best[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (hipMemcpy(par, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemsetAsync(msk, 0, n, s) != hipSuccess) st = DECONV_ERR_HIP;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == DECONV_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
       st = DECONV_ERR_HIP;
-    const int kReps = 4;
+    const int kReps = 5;
     for (int pass = 0; pass < 2 && st == DECONV_OK; ++pass) {
-      for (int k = 0; k < 2 && st == DECONV_OK; ++k) {
+      for (int k = 0; k < 3 && st == DECONV_OK; ++k) {
         if (pass == 0) p->row_groups = p->row_sets[k];
         else p->col_groups = p->col_sets[k];
         for (int r = 0; r <= kReps && st == DECONV_OK; ++r) {
@@ -911,8 +946,9 @@ static deconv_status autotune(deconv_plan_s* p) {
     (void)hipFree(msk);
     (void)hipFree(par);
     if (st != DECONV_OK) return st;
-    rs = rows ? (best[0][0] < best[0][1] ? 0 : 1) : 1;
-    cs = cols ? (best[1][0] < best[1][1] ? 0 : 1) : 1;
+    auto pick = [](const double* t) { return t[0] < t[1] ? (t[0] < t[2] ? 0 : 2) : (t[1] < t[2] ? 1 : 2); };
+    rs = rows ? pick(best[0]) : 1;
+    cs = cols ? pick(best[1]) : 1;
     cache_store(p->opt.tune_cache, key, rs, cs);
   }
   p->row_sched = rs;

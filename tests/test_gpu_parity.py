@@ -238,3 +238,18 @@ def test_autotuned_schedules_agree(tmp_path):
     p2 = binding.Plan([desc(p) for p in probs], tune_cache=cache)
     assert p2.schedule() == p1.schedule()
     assert len(open(cache).read().splitlines()) == 1
+
+
+def test_hybrid_schedule_agrees(torch_cuda):
+    """The hybrid launch shape (short lengths share one launch, lengths with
+    many tiles keep their own) gives the iterates of one launch per length."""
+    probs = [_small(512, 512, 7, synth.MASK_BOUNDARY, seed=300 + b, blur="gauss") for b in range(8)]
+    probs += [_small(64, 96, 5, synth.MASK_DECIMATE, seed=310), _small(96, 64, 9, synth.MASK_EXPLICIT, seed=311),
+              _small(128, 128, 5, synth.MASK_BOUNDARY, seed=312)]
+    a = gpu_run(probs, 12, schedule=1)
+    c = gpu_run(probs, 12, schedule=3)
+    assert c["plan"].schedule() == (3, 3)
+    for i in range(len(probs)):
+        assert rel_l2(c["x"][i], a["x"][i]) <= 1e-6, i
+    r = oracle_run(probs[8], 12)
+    assert_parity(c["x"][8], r["x"], what="hybrid small image x")
