@@ -475,10 +475,25 @@ __device__ __forceinline__ float vsoft_scale(float n2, float tau, float tau2) {
   return n2 > tau2 ? 1.0f - tau * __builtin_amdgcn_rsqf(n2) : 0.f;
 }
 
-// PLAIN: an iteration that neither checks residuals nor stores v, x or u
-// (most iterations between two residual checks); the flags are then
-// compile-time constants.
-template <int L, bool PLAIN, int RT = rt_for(L)>
+// Row-pass instantiations by the work an iteration asks for, so that the
+// common cases run with their flags as compile-time constants:
+//   RV_PLAIN   ROW_ITER, no residuals, no stores of v, x or u (most
+//              iterations between two residual checks);
+//   RV_STOREV  ROW_ITER storing v only (the iteration before a check);
+//   RV_CHECK   ROW_ITER with residuals and stores of v and x (a check);
+//   RV_GENERIC every mode and flag from the arguments.
+enum { RV_PLAIN = 0, RV_STOREV = 1, RV_CHECK = 2, RV_GENERIC = 3 };
+
+// the variant a launch with these arguments needs
+__host__ __device__ inline int row_variant(const RowArgs& a) {
+  if (a.mode != ROW_ITER || a.u_out || a.last) return RV_GENERIC;
+  if (!a.check && !a.store_v && !a.store_x) return RV_PLAIN;
+  if (!a.check && a.store_v && !a.store_x) return RV_STOREV;
+  if (a.check && a.store_v && a.store_x) return RV_CHECK;
+  return RV_GENERIC;
+}
+
+template <int L, int V, int RT = rt_for(L)>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
   using PM = PixMap<L>;
   constexpr int LS = lstride(L);
@@ -486,24 +501,25 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   const unsigned tid = threadIdx.x;
   __builtin_assume(tid < (unsigned)kNTR);
   const ImgMeta mt = a.meta[img];
-  if (!PLAIN && a.mode == ROW_INNER) {
+  constexpr bool GEN = V == RV_GENERIC;
+  if (GEN && a.mode == ROW_INNER) {
     row_inner<L, RT>(a, mt, r0, lds);
     return;
   }
   const int M = mt.m;
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
-  const bool check = !PLAIN && a.check;
-  const bool uonly = !PLAIN && a.mode == ROW_UONLY;
-  const bool store_v = !PLAIN && a.store_v;
-  const bool store_x = !PLAIN && a.store_x;
+  const bool check = V == RV_CHECK || (GEN && a.check);
+  const bool uonly = GEN && a.mode == ROW_UONLY;
+  const bool store_v = V == RV_STOREV || V == RV_CHECK || (GEN && a.store_v);
+  const bool store_x = V == RV_CHECK || (GEN && a.store_x);
   // image-local bases (uniform) with 32-bit offsets below
   const float2* __restrict__ d_in = a.d_in + mt.px;
   float2* __restrict__ d_out = a.d_out + mt.px;
   float* __restrict__ yt = a.yt + mt.px;
   float2* __restrict__ vst = a.v + mt.px;
   float* __restrict__ x_out = store_x ? a.x_out + mt.px : nullptr;
-  float2* __restrict__ u_out = (!PLAIN && a.u_out) ? a.u_out + mt.px : nullptr;
+  float2* __restrict__ u_out = (GEN && a.u_out) ? a.u_out + mt.px : nullptr;
   float2* buf = lds;
   const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
@@ -514,7 +530,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   float2 wreg[KP];
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
-  if (PLAIN || a.mode == ROW_ITER || uonly) {
+  if (!GEN || a.mode == ROW_ITER || uonly) {
     gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
     __syncthreads();
 #if DCV_EARLY_STATE
@@ -613,7 +629,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
       out[0] = rdd; out[1] = rvd; out[2] = rzd;
     }
   }
-  if (!PLAIN && (a.last || uonly)) return;
+  if (GEN && (a.last || uonly)) return;
   // prologue of the next x-step: pack ytilde + i mu D^T(v - d)
   row_prologue<L, RT, KP>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
                           [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); });
@@ -624,30 +640,30 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
 #ifndef DCV_ROW_WAVES
 #define DCV_ROW_WAVES 1
 #endif
-template <int L, bool PLAIN, int RT = rt_for(L)>
+template <int L, int V, int RT = rt_for(L)>
 __global__ void __launch_bounds__(kNTR, DCV_ROW_WAVES) row_kernel(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  row_tile<L, PLAIN, RT>(a, t.x, t.y, lds);
+  row_tile<L, V, RT>(a, t.x, t.y, lds);
 }
 
 // one launch for tiles of every line length: dispatch on the tile's length
-template <bool PLAIN, int L0, int... Ls>
+template <int V, int L0, int... Ls>
 __device__ __forceinline__ void row_dispatch(const RowArgs& a, int L, int img, int r0, float2* lds) {
   if (L == L0) {
-    row_tile<L0, PLAIN>(a, img, r0, lds);
+    row_tile<L0, V>(a, img, r0, lds);
     return;
   }
-  if constexpr (sizeof...(Ls) > 0) row_dispatch<PLAIN, Ls...>(a, L, img, r0, lds);
+  if constexpr (sizeof...(Ls) > 0) row_dispatch<V, Ls...>(a, L, img, r0, lds);
 }
 
-template <bool PLAIN, int... Ls>
+template <int V, int... Ls>
 __global__ void __launch_bounds__(kNTR) row_kernel_multi(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  row_dispatch<PLAIN, Ls...>(a, a.meta[t.x].n, t.x, t.y, lds);
+  row_dispatch<V, Ls...>(a, a.meta[t.x].n, t.x, t.y, lds);
 }
 
 // ---------------------------------------------------------------------------

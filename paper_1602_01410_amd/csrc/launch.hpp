@@ -40,16 +40,44 @@ inline hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void
 }
 
 // L = 0 launches the kernel that dispatches on each tile's length.
-// launch_row picks the plain-iteration instantiation when the arguments ask
-// for no residuals and no stores of v, x or u.
+// launch_row picks the row-pass variant the arguments need (row_variant).
 size_t row_lds_bytes(int L, int rt = 0);
 size_t col_lds_bytes(int L);
 // rt: rows per tile of the group (0 or rt_for(L): the default; rt_half(L) for
 // the lengths of DCV_FOR_EACH_HALF_RT_LEN)
 hipError_t launch_row(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
-hipError_t launch_row_plain(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
-                            hipEvent_t e1);
+// one row-pass variant (RV_*): instantiated in its own translation unit
+template <int V>
+hipError_t launch_row_variant(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
+                              hipEvent_t e1) {
+  void* args[] = {&a};
+  if (L == 0) return launch_lds(row_kernel_multi<V, DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
+  if (rt > 0 && rt != rt_for(L)) {
+    switch (L) {
+#define DCV_CASE(n) \
+  case n: return rt == rt_half(n) ? launch_lds(row_kernel<n, V, rt_half(n)>, grid, lds, s, args, kNTR, e0, e1) \
+                                  : hipErrorInvalidValue;
+      DCV_FOR_EACH_HALF_RT_LEN(DCV_CASE)
+#undef DCV_CASE
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (L) {
+#define DCV_CASE(n) case n: return launch_lds(row_kernel<n, V>, grid, lds, s, args, kNTR, e0, e1);
+    DCV_FOR_EACH_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+extern template hipError_t launch_row_variant<RV_PLAIN>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
+                                                        hipEvent_t);
+extern template hipError_t launch_row_variant<RV_STOREV>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
+                                                         hipEvent_t);
+extern template hipError_t launch_row_variant<RV_CHECK>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
+                                                        hipEvent_t);
+extern template hipError_t launch_row_variant<RV_GENERIC>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
+                                                          hipEvent_t);
 hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a);

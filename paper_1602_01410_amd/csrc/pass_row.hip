@@ -1,4 +1,4 @@
-// Instantiations and launcher of one pass (see launch.hpp).
+// Row-pass launcher and its generic instantiation (see launch.hpp).
 #include "launch.hpp"
 
 namespace dcv {
@@ -12,27 +12,16 @@ size_t row_lds_bytes(int L, int rt) {
   return 0;
 }
 
+template hipError_t launch_row_variant<RV_GENERIC>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
+                                                   hipEvent_t);
+
 hipError_t launch_row(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0, hipEvent_t e1) {
-  const bool plain = a.mode == ROW_ITER && !a.check && !a.store_v && !a.store_x && !a.u_out && !a.last;
-  if (plain) return launch_row_plain(L, rt, grid, lds, s, a, e0, e1);
-  void* args[] = {&a};
-  if (L == 0) return launch_lds(row_kernel_multi<false, DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
-  if (rt > 0 && L > 0 && rt != rt_for(L)) {
-    switch (L) {
-#define DCV_CASE(n) \
-  case n: return rt == rt_half(n) ? launch_lds(row_kernel<n, false, rt_half(n)>, grid, lds, s, args, kNTR, e0, e1) \
-                                  : hipErrorInvalidValue;
-      DCV_FOR_EACH_HALF_RT_LEN(DCV_CASE)
-#undef DCV_CASE
-    }
-    return hipErrorInvalidValue;
+  switch (row_variant(a)) {
+    case RV_PLAIN: return launch_row_variant<RV_PLAIN>(L, rt, grid, lds, s, a, e0, e1);
+    case RV_STOREV: return launch_row_variant<RV_STOREV>(L, rt, grid, lds, s, a, e0, e1);
+    case RV_CHECK: return launch_row_variant<RV_CHECK>(L, rt, grid, lds, s, a, e0, e1);
+    default: return launch_row_variant<RV_GENERIC>(L, rt, grid, lds, s, a, e0, e1);
   }
-  switch (L) {
-#define DCV_CASE(n) case n: return launch_lds(row_kernel<n, false>, grid, lds, s, args, kNTR, e0, e1);
-    DCV_FOR_EACH_LEN(DCV_CASE)
-#undef DCV_CASE
-  }
-  return hipErrorInvalidValue;
 }
 
 }  // namespace dcv
