@@ -197,6 +197,35 @@ __device__ __forceinline__ bool pixel_observed(const ImgMeta& mt, const RowObs& 
   return r.row_ok & (j >= mt.b) & (j < mt.n - mt.b) & (!r.decim | divisible(j - mt.b, mt.decim, mt.dmagic));
 }
 
+// Stores of pass outputs that another kernel reads.  With the
+// non-temporal hint (NT = true) the lines stream out instead of staying
+// dirty in L2 until the end-of-kernel write-back; that pays for the row
+// pass's full-line state writes.  Bits of DCV_NT_STORE: 1 row-pass state
+// (d, z), 2 row-pass spectra, 4 column-pass spectra.
+#ifndef DCV_NT_STORE
+#define DCV_NT_STORE 1
+#endif
+typedef float dcv_f4v __attribute__((ext_vector_type(4)));
+typedef float dcv_f2v __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ void st_out(float4* p, float4 v) {
+  if constexpr (NT) __builtin_nontemporal_store(dcv_f4v{v.x, v.y, v.z, v.w}, reinterpret_cast<dcv_f4v*>(p));
+  else *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st_out(float2* p, float2 v) {
+  if constexpr (NT) __builtin_nontemporal_store(dcv_f2v{v.x, v.y}, reinterpret_cast<dcv_f2v*>(p));
+  else *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st_out(float* p, float v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+constexpr bool kNtRowState = (DCV_NT_STORE & 1) != 0;
+constexpr bool kNtRowSpec = (DCV_NT_STORE & 2) != 0;
+constexpr bool kNtColSpec = (DCV_NT_STORE & 4) != 0;
+
 __device__ __forceinline__ int wrapi(int i, int M) { return i < 0 ? i + M : (i >= M ? i - M : i); }
 
 // reciprocal with one Newton step (error below 1 ulp of the exact division)
@@ -325,8 +354,8 @@ __device__ __forceinline__ void split_store(float4* __restrict__ sout, const flo
     if (l < nr && blk < nb && kx < nh) {
       const float2 cf = buf[l * LS + lpad(kx)];
       const float2 cm = buf[l * LS + lpad(kx == 0 ? 0 : L - kx)];
-      sout[((__umul24(blk, M) + r0 + l) << logC) + c] =
-          make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x));
+      st_out<kNtRowSpec>(sout + (((__umul24(blk, M) + r0 + l) << logC) + c),
+             make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x)));
     }
   }
 }
@@ -579,7 +608,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
         const float dh = uh - vh, dv = uv - vv;
         wreg[k] = make_float2(vh - dh, vv - dv);
         if (l >= 1) {
-          d_out[pix] = uonly ? make_float2(uh, uv) : make_float2(dh, dv);
+          st_out<kNtRowState>(d_out + pix, uonly ? make_float2(uh, uv) : make_float2(dh, dv));
           if (check && !uonly) {
             rd += (dh - dd[k].x) * (dh - dd[k].x) + (dv - dd[k].y) * (dv - dd[k].y);
             const float2 vo = vst[pix];
@@ -591,7 +620,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
           if (!pixel_observed(mt, ro, ro.explicit_mask ? a.mask + mt.px + i * L : nullptr, j)) {
             const float hx = buf[(l - 1) * LS + lj].y;
             yn = yo[k] + alpha * (hx - yo[k]);
-            yt[pix] = yn;
+            st_out<kNtRowState>(yt + pix, yn);
             if (check) rz += (yn - yo[k]) * (yn - yo[k]);
           }
           ynew[k] = yn;
@@ -747,7 +776,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
       const int i = q / C, c = q - i * C;
       const float2 X = buf[(2 * c) * LS + lpad(i)];
       const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-      sout[row_block_index(mt, i, nbc) + c * mt.rt] = make_float4(X.x, X.y, Q.x, Q.y);
+      st_out<kNtColSpec>(sout + (row_block_index(mt, i, nbc) + c * mt.rt), make_float4(X.x, X.y, Q.x, Q.y));
     }
   }
 }
