@@ -222,6 +222,37 @@ __device__ __forceinline__ void st_out(float* p, float v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
+// The same hint on loads (bits: 1 row-pass state, 2 row-pass spectra, 4
+// column-pass inputs); measured to pay for the row-pass state only.
+#ifndef DCV_NT_LOAD
+#define DCV_NT_LOAD 1
+#endif
+template <bool NT>
+__device__ __forceinline__ float4 ld_in(const float4* p) {
+  if constexpr (NT) {
+    const dcv_f4v v = __builtin_nontemporal_load(reinterpret_cast<const dcv_f4v*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float2 ld_in(const float2* p) {
+  if constexpr (NT) {
+    const dcv_f2v v = __builtin_nontemporal_load(reinterpret_cast<const dcv_f2v*>(p));
+    return make_float2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float ld_in(const float* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+constexpr bool kNtLdRowState = (DCV_NT_LOAD & 1) != 0;
+constexpr bool kNtLdRowSpec = (DCV_NT_LOAD & 2) != 0;
+constexpr bool kNtLdCol = (DCV_NT_LOAD & 4) != 0;
 constexpr bool kNtRowState = (DCV_NT_STORE & 1) != 0;
 constexpr bool kNtRowSpec = (DCV_NT_STORE & 2) != 0;
 constexpr bool kNtColSpec = (DCV_NT_STORE & 4) != 0;
@@ -290,7 +321,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
     const int l = q % RT, kx = q / RT;
     dst[k] = -1;
     if (l < nr && kx < nh) {
-      g[k] = blkp[q];
+      g[k] = ld_in<kNtLdRowSpec>(blkp + q);
       dst[k] = l * LS + kx;
     }
   }
@@ -571,8 +602,8 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
       const int l = PM::row(k, tid), j = PM::col(k, tid);
       if (l <= nr) {
         const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
-        dd[k] = d_in[pix];
-        if (l >= 1) yo[k] = yt[pix];
+        dd[k] = ld_in<kNtLdRowState>(d_in + pix);
+        if (l >= 1) yo[k] = ld_in<kNtLdRowState>(yt + pix);
       }
     }
     fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
@@ -585,8 +616,8 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
       const int l = PM::row(k, tid), j = PM::col(k, tid);
       if (l <= nr) {
         const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
-        dd[k] = d_in[pix];
-        if (l >= 1) yo[k] = yt[pix];
+        dd[k] = ld_in<kNtLdRowState>(d_in + pix);
+        if (l >= 1) yo[k] = ld_in<kNtLdRowState>(yt + pix);
       }
     }
 #endif
@@ -698,46 +729,66 @@ __global__ void __launch_bounds__(kNTR) row_kernel_multi(RowArgs a) {
 // ---------------------------------------------------------------------------
 // column pass
 // ---------------------------------------------------------------------------
+// Registers of one column tile between its loads and its use: the (Y, mu G)
+// column spectra, the blur spectrum and the |D|^2 sums of its frequencies.
 template <int L>
-__device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, float2* lds) {
+struct ColLoad {
+  static constexpr int C = c_for(L);
+  static constexpr int NQ = (L * C + kNTC - 1) / kNTC;
+  float4 g[NQ];
+  float2 Hk[NQ];
+  float dsum[NQ];
+};
+
+// issue every load of tile (img, blk)
+template <int L>
+__device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, int blk, ColLoad<L>& r) {
   constexpr int C = c_for(L);
-  constexpr int LS = lstride(L);
-  constexpr int NQ = (L * C + kNTC - 1) / kNTC;
-  const ImgMeta mt = a.meta[img];
-  float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTC>(lds + 2 * C * LS, a.tw + mt.twc);
+  constexpr int NQ = ColLoad<L>::NQ;
   const long long base = mt.sp + (long long)blk * L * C;
   const float4* __restrict__ sin = a.spec_in + base;
   const float2* __restrict__ hh = a.hh + mt.hh + (long long)blk * L * C;
   const float* __restrict__ dv2 = a.tab + mt.tab;
   const float* __restrict__ dh2 = dv2 + L;
-  const float mu = a.mu[img];
-  // every load of the tile first: spectra, blur spectrum, |D|^2 terms
-  float4 g[NQ];
-  float2 Hk[NQ];
-  float dsum[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = threadIdx.x + k * kNTC;
     if (q < L * C) {
       const int ky = q / C, c = q - ky * C;
-      g[k] = sin[q];
-      Hk[k] = hh[q];
-      dsum[k] = dh2[blk * C + c] + dv2[ky];
+      r.g[k] = ld_in<kNtLdCol>(sin + q);
+      r.Hk[k] = ld_in<kNtLdCol>(hh + q);
+      r.dsum[k] = dh2[blk * C + c] + dv2[ky];
     }
   }
+}
+
+// the column spectra into the LDS lines (Y in line 2c, mu G in line 2c+1)
+template <int L>
+__device__ __forceinline__ void col_fill(const ColLoad<L>& r, float2* buf) {
+  constexpr int C = c_for(L);
+  constexpr int LS = lstride(L);
 #pragma unroll
-  for (int k = 0; k < NQ; ++k) {
+  for (int k = 0; k < ColLoad<L>::NQ; ++k) {
     const int q = threadIdx.x + k * kNTC;
     if (q < L * C) {
       const int i = q / C, c = q - i * C;
-      buf[(2 * c) * LS + lpad(i)] = make_float2(g[k].x, g[k].y);
-      buf[(2 * c + 1) * LS + lpad(i)] = make_float2(g[k].z, g[k].w);
+      buf[(2 * c) * LS + lpad(i)] = make_float2(r.g[k].x, r.g[k].y);
+      buf[(2 * c + 1) * LS + lpad(i)] = make_float2(r.g[k].z, r.g[k].w);
     }
   }
+}
+
+// forward column DFTs, x-step solve, Q = H X, inverse DFTs, store (X, Q);
+// the caller has filled the lines (not yet synchronised)
+template <int L>
+__device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta& mt, int blk, float muv,
+                                                const float2* Hk, const float* dsum, float2* buf, const float2* tw) {
+  constexpr int C = c_for(L);
+  constexpr int LS = lstride(L);
+  constexpr int NQ = ColLoad<L>::NQ;
+  const long long base = mt.sp + (long long)blk * L * C;
   __syncthreads();
   fft_lines<L, false, kNTC, 2 * C>(buf, 2 * C, tw);
-
   const float scale = 1.0f / ((float)L * (float)mt.n);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
@@ -754,7 +805,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
         // x-step: (conj(H) Y + G) / (|H|^2 + mu |D|^2); warm start (eq. (ini_x)):
         // conj(H) Y / (|H|^2 + tau)
         const float2 Gk = a.warm ? make_float2(0.f, 0.f) : G;
-        const float den = a.warm ? h2 + a.warm_tau : h2 + mu * dsum[k];
+        const float den = a.warm ? h2 + a.warm_tau : h2 + muv * dsum[k];
         const float inv = scale * frcp(den);
         X = make_float2((H.x * Y.x + H.y * Y.y + Gk.x) * inv, (H.x * Y.y - H.y * Y.x + Gk.y) * inv);
         Q = cmul(H, X);
@@ -779,6 +830,18 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
       st_out<kNtColSpec>(sout + (row_block_index(mt, i, nbc) + c * mt.rt), make_float4(X.x, X.y, Q.x, Q.y));
     }
   }
+}
+
+template <int L>
+__device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, float2* lds) {
+  constexpr int C = c_for(L);
+  const ImgMeta mt = a.meta[img];
+  float2* buf = lds;
+  const float2* tw = twiddle_table<L, kNTC>(lds + 2 * C * lstride(L), a.tw + mt.twc);
+  ColLoad<L> r;
+  col_load<L>(a, mt, blk, r);
+  col_fill<L>(r, buf);
+  col_solve_store<L>(a, mt, blk, a.mu[img], r.Hk, r.dsum, buf, tw);
 }
 
 template <int L>
