@@ -189,11 +189,15 @@ deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const flo
 
 /* Copy the resumable state w = [z; v; d] (Appendix B) out of / into the plan.
    ytilde: packed float (observed pixels hold y); v, d: packed float2 per
-   pixel (horizontal, vertical).  Import also needs h for the spectrum (device
-   float, packed) and makes deconv_admm_continue start from this state; plans
-   with explicit masks need a previous deconv_admm_run (its mask is reused). */
+   pixel (horizontal, vertical).  Import also takes the observation mask
+   (device bytes, packed; null for plans whose masks are all implicit, and
+   kept, like deconv_admm_run's, for deconv_admm_continue) and h for the
+   spectrum (device float, packed); the buffers are copied, the caller keeps
+   them.  After an import deconv_admm_continue starts from this state; the
+   checkpoints of an earlier run are dropped.  Export needs a run or an import
+   first (DECONV_ERR_STATE). */
 deconv_status deconv_state_export(deconv_plan p, float* ytilde, float* v, float* d);
-deconv_status deconv_state_import(deconv_plan p, const float* h, const float* mu,
+deconv_status deconv_state_import(deconv_plan p, const uint8_t* mask, const float* h,
                                   const float* ytilde, const float* v, const float* d);
 
 /*

@@ -225,8 +225,8 @@ class Plan:
         _check(lib().deconv_plan_kernel_times(self.handle, out), "kernel_times")
         return tuple(out)
 
-    def state_import(self, h, mu, yt, v, d):
-        _check(lib().deconv_state_import(self.handle, _ptr(h), _ptr(mu), _ptr(yt), _ptr(v), _ptr(d)),
+    def state_import(self, mask, h, yt, v, d):
+        _check(lib().deconv_state_import(self.handle, _ptr(mask), _ptr(h), _ptr(yt), _ptr(v), _ptr(d)),
                "state_import")
 
     # helpers to split packed outputs per image

@@ -1281,11 +1281,12 @@ extern "C" deconv_status deconv_state_export(deconv_plan p, float* ytilde, float
   return DECONV_OK;
 }
 
-extern "C" deconv_status deconv_state_import(deconv_plan p, const float* h, const float* mu, const float* ytilde,
-                                             const float* v, const float* d) {
-  if (!p || !h || !mu || !ytilde || !v || !d) return DECONV_ERR_INVALID_ARG;
-  if (needs_mask(p) && !p->mask) return DECONV_ERR_STATE;
+extern "C" deconv_status deconv_state_import(deconv_plan p, const uint8_t* mask, const float* h,
+                                             const float* ytilde, const float* v, const float* d) {
+  if (!p || !h || !ytilde || !v || !d) return DECONV_ERR_INVALID_ARG;
+  if (needs_mask(p) && !mask) return DECONV_ERR_INVALID_ARG;
   hipStream_t s = p->stream;
+  p->mask = mask;
   const size_t n = (size_t)p->total_px;
   STCHK(setup_spectrum(p, h, nullptr));
   HIPCHK(hipMemcpyAsync(p->yt, ytilde, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
