@@ -116,8 +116,8 @@ static const float2* cached_twiddles(int L) {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-// one launch of a pass: line length L (0 = several lengths, dispatched per
-// tile) over tiles [tile0, tile0 + ntiles) of the tile table
+// one launch of a pass: line length L (-Lmax = several lengths up to Lmax,
+// dispatched per tile) over tiles [tile0, tile0 + ntiles) of the tile table
 struct Group {
   int L;
   long long tile0;
@@ -416,8 +416,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     xcd_schedule(imgs, p->h_tiles);
     dst.push_back(Group{L, t0, (int)((long long)p->h_tiles.size() - t0), lds, rt});
   };
-  add_group(p->row_sets[1], widths.size() == 1 ? *widths.begin() : 0, rlds, rt_tiles, grt);
-  add_group(p->col_sets[1], heights.size() == 1 ? *heights.begin() : 0, clds, ct_tiles, 0);
+  add_group(p->row_sets[1], widths.size() == 1 ? *widths.begin() : -*widths.rbegin(), rlds, rt_tiles, grt);
+  add_group(p->col_sets[1], heights.size() == 1 ? *heights.begin() : -*heights.rbegin(), clds, ct_tiles, 0);
   if (widths.size() == 1) {
     p->row_sets[0] = p->row_sets[1];
   } else {
@@ -461,7 +461,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
       if (small.count(L)) sel[b] = tiles[b];
     }
     for (int L : small) lds = std::max(lds, rows ? row_lds_bytes(L) : col_lds_bytes(L));
-    add_group(dst, 0, lds, sel, 0);
+    add_group(dst, -*small.rbegin(), lds, sel, 0);
     for (int L : lens) {
       if (small.count(L)) continue;
       std::vector<std::vector<TileRef>> one(B);

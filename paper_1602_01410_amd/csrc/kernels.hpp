@@ -718,8 +718,18 @@ __device__ __forceinline__ void row_dispatch(const RowArgs& a, int L, int img, i
   if constexpr (sizeof...(Ls) > 0) row_dispatch<V, Ls...>(a, L, img, r0, lds);
 }
 
+// The multi-length kernels hold the code of every length they dispatch to;
+// left alone the register allocator sizes them for the union, which can
+// cost a workgroup per compute unit.  They are held to the occupancy of the
+// single-length kernels instead.
+#ifndef DCV_MULTI_ROW_WAVES
+#define DCV_MULTI_ROW_WAVES 4
+#endif
+#ifndef DCV_MULTI_COL_WAVES
+#define DCV_MULTI_COL_WAVES 4
+#endif
 template <int V, int... Ls>
-__global__ void __launch_bounds__(kNTR) row_kernel_multi(RowArgs a) {
+__global__ void __launch_bounds__(kNTR, DCV_MULTI_ROW_WAVES) row_kernel_multi(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
@@ -862,7 +872,7 @@ __device__ __forceinline__ void col_dispatch(const ColArgs& a, int L, int img, i
 }
 
 template <int... Ls>
-__global__ void __launch_bounds__(kNTC) col_kernel_multi(ColArgs a) {
+__global__ void __launch_bounds__(kNTC, DCV_MULTI_COL_WAVES) col_kernel_multi(ColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;

@@ -17,7 +17,13 @@
   8, 12, 16, 18, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256, 288, 384, 512, 576, 768, 1024, 1152, \
       1536, 2048
 
+// the lengths up to kShortLenMax: a multi-length launch whose lengths are all
+// short dispatches over these only (fewer registers than the full list)
+#define DCV_SHORT_LEN_ARGS 8, 12, 16, 18, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256, 288
+
 namespace dcv {
+
+constexpr int kShortLenMax = 288;
 
 inline bool supported_len(int L) {
   switch (L) {
@@ -39,7 +45,8 @@ inline hipError_t launch_lds(K kernel, int grid, size_t lds, hipStream_t s, void
   return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(nt), args, lds, s);
 }
 
-// L = 0 launches the kernel that dispatches on each tile's length.
+// L <= 0 launches a kernel that dispatches on each tile's length; -L is the
+// longest length among the tiles (0: unknown, any length).
 // launch_row picks the row-pass variant the arguments need (row_variant).
 size_t row_lds_bytes(int L, int rt = 0);
 size_t col_lds_bytes(int L);
@@ -52,7 +59,9 @@ template <int V>
 hipError_t launch_row_variant(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
                               hipEvent_t e1) {
   void* args[] = {&a};
-  if (L == 0) return launch_lds(row_kernel_multi<V, DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
+  if (L < 0 && -L <= kShortLenMax)
+    return launch_lds(row_kernel_multi<V, DCV_SHORT_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
+  if (L <= 0) return launch_lds(row_kernel_multi<V, DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
   if (rt > 0 && rt != rt_for(L)) {
     switch (L) {
 #define DCV_CASE(n) \

@@ -5,7 +5,7 @@ namespace dcv {
 
 hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a) {
   void* args[] = {&a};
-  if (L == 0) return launch_lds(bwd_col_kernel_multi<DCV_LEN_ARGS>, grid, lds, s, args, kNTC);
+  if (L <= 0) return launch_lds(bwd_col_kernel_multi<DCV_LEN_ARGS>, grid, lds, s, args, kNTC);
   switch (L) {
 #define DCV_CASE(n) case n: return launch_lds(bwd_col_kernel<n>, grid, lds, s, args, kNTC);
     DCV_FOR_EACH_LEN(DCV_CASE)
