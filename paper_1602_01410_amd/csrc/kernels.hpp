@@ -68,9 +68,10 @@ __host__ __device__ constexpr int c_for(int L) {
 #endif
 constexpr int kTwLds = DCV_TW_GLOBAL ? 0 : 1;
 // row pass: issue the epilogue's state loads before the inverse transform
-// (1) or after it (0, fewer live registers)
+// (1) or after it (0: fewer live registers, which lets three 512-thread
+// workgroups share a compute unit; measured faster on MI355X)
 #ifndef DCV_EARLY_STATE
-#define DCV_EARLY_STATE 1
+#define DCV_EARLY_STATE 0
 #endif
 __host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
   return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLds * L;
@@ -697,8 +698,10 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
 
 // Tile tables are built on the host in dispatch order (XCD-interleaved, see
 // deconv.hip); entries with image -1 are padding.
+// minimum waves per SIMD the row kernels are compiled for: 6 = three
+// workgroups of 512 threads per compute unit (at most 80 registers)
 #ifndef DCV_ROW_WAVES
-#define DCV_ROW_WAVES 1
+#define DCV_ROW_WAVES 6
 #endif
 template <int L, int V, int RT = rt_for(L)>
 __global__ void __launch_bounds__(kNTR, DCV_ROW_WAVES) row_kernel(RowArgs a) {
