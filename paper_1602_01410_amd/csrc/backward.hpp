@@ -244,7 +244,7 @@ __device__ __forceinline__ void bwd_row_dispatch(const BwdRowArgs& a, int L, int
 }
 
 template <int... Ls>
-__global__ void __launch_bounds__(kNTR) bwd_row_kernel_multi(BwdRowArgs a) {
+__global__ void __launch_bounds__(kNTR, DCV_MULTI_ROW_WAVES) bwd_row_kernel_multi(BwdRowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0) return;
@@ -338,7 +338,7 @@ __device__ __forceinline__ void bwd_col_dispatch(const BwdColArgs& a, int L, int
 }
 
 template <int... Ls>
-__global__ void __launch_bounds__(kNTC) bwd_col_kernel_multi(BwdColArgs a) {
+__global__ void __launch_bounds__(kNTC, DCV_MULTI_COL_WAVES) bwd_col_kernel_multi(BwdColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0) return;

@@ -67,6 +67,11 @@ __host__ __device__ constexpr int c_for(int L) {
 #define DCV_TW_GLOBAL 1
 #endif
 constexpr int kTwLds = DCV_TW_GLOBAL ? 0 : 1;
+// row pass: full tiles get their own copy of the tile code with the row
+// count as a constant (1) or share the code of the ragged last tiles (0)
+#ifndef DCV_FULL_TILES
+#define DCV_FULL_TILES 0
+#endif
 // row pass: issue the epilogue's state loads before the inverse transform
 // (1) or after it (0: fewer live registers, which lets three 512-thread
 // workgroups share a compute unit; measured faster on MI355X)
@@ -79,7 +84,12 @@ __host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
 // Lengths that also have row tiles of half the rows (rt_for(L) / 2), for
 // plans with too few tiles to fill the chip
 #define DCV_FOR_EACH_HALF_RT_LEN(X) X(512) X(1024) X(2048)
-__host__ __device__ constexpr int rt_half(int L) { return rt_for(L) / 2 > 0 ? rt_for(L) / 2 : 1; }
+#ifndef DCV_RT_SPLIT
+#define DCV_RT_SPLIT 2
+#endif
+__host__ __device__ constexpr int rt_half(int L) {
+  return rt_for(L) / DCV_RT_SPLIT > 0 ? rt_for(L) / DCV_RT_SPLIT : 1;
+}
 __host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLds * L; }
 
 // the twiddle table a workgroup uses for length L (caller synchronises)
@@ -554,21 +564,18 @@ __host__ __device__ inline int row_variant(const RowArgs& a) {
   return RV_GENERIC;
 }
 
-template <int L, int V, int RT = rt_for(L)>
-__device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
+// One row tile of nr <= RT own rows (nr == RT is passed as a literal for the
+// full tiles, so that their row bounds fold away).
+template <int L, int V, int RT>
+__device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& mt, int img, int r0, int nr,
+                                              float2* lds) {
   using PM = PixMap<L>;
   constexpr int LS = lstride(L);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;  // pixels per thread (own rows + 1 halo)
   const unsigned tid = threadIdx.x;
   __builtin_assume(tid < (unsigned)kNTR);
-  const ImgMeta mt = a.meta[img];
   constexpr bool GEN = V == RV_GENERIC;
-  if (GEN && a.mode == ROW_INNER) {
-    row_inner<L, RT>(a, mt, r0, lds);
-    return;
-  }
   const int M = mt.m;
-  const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   const bool check = V == RV_CHECK || (GEN && a.check);
   const bool uonly = GEN && a.mode == ROW_UONLY;
@@ -694,6 +701,22 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
   // prologue of the next x-step: pack ytilde + i mu D^T(v - d)
   row_prologue<L, RT, KP>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
                           [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); });
+}
+
+template <int L, int V, int RT = rt_for(L)>
+__device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
+  const ImgMeta mt = a.meta[img];
+  if (V == RV_GENERIC && a.mode == ROW_INNER) {
+    row_inner<L, RT>(a, mt, r0, lds);
+    return;
+  }
+#if DCV_FULL_TILES
+  if (r0 + RT <= mt.m) {
+    row_tile_rows<L, V, RT>(a, mt, img, r0, RT, lds);
+    return;
+  }
+#endif
+  row_tile_rows<L, V, RT>(a, mt, img, r0, min(RT, mt.m - r0), lds);
 }
 
 // Tile tables are built on the host in dispatch order (XCD-interleaved, see
