@@ -333,10 +333,13 @@ static bool has_half_rt(int L) {
   return false;
 }
 
-// A plan whose images share one width and that has fewer row tiles than two
-// per compute unit (one 1024^2 image: 256) takes tiles of half the rows:
-// twice the workgroups, each with a shorter chain of dependent steps.  Not
-// with checkpoints: the reverse pass uses the default tiles.
+// A plan whose images share one width takes tiles of half the rows (twice
+// the workgroups, each with a shorter chain of dependent steps) when it has
+// fewer default row tiles than two per compute unit (one 1024^2 image: 256),
+// or fewer than six when the half tiles still hold 4 rows or more (measured:
+// 16 x 512^2 gains 13%; 2048^2, whose half tiles are single rows with a whole
+// halo line each, loses 9%).  Not with checkpoints: the reverse pass uses the
+// default tiles.
 static bool use_half_rt(const deconv_plan_s* p) {
   std::set<int> ws;
   long long tiles = 0;
@@ -344,7 +347,8 @@ static bool use_half_rt(const deconv_plan_s* p) {
     ws.insert(d.width);
     tiles += (d.height + rt_for(d.width) - 1) / rt_for(d.width);
   }
-  return ws.size() == 1 && has_half_rt(*ws.begin()) && tiles < 2 * num_cus() && p->opt.ckpt_every == 0;
+  if (ws.size() != 1 || !has_half_rt(*ws.begin()) || p->opt.ckpt_every != 0) return false;
+  return tiles < (rt_half(*ws.begin()) >= 4 ? 6 : 2) * (long long)num_cus();
 }
 
 // build per-image metadata and the workspace layout

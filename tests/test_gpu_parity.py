@@ -94,6 +94,21 @@ def test_half_height_row_tiles(torch_cuda, shape):
     assert_parity(g2["x"][0], r2["x"], what="%dx%d x, 2 passes + adaptive" % (M, N))
 
 
+def test_half_height_row_tiles_batch(torch_cuda):
+    """Several images of one width whose half tiles keep 4 rows (six 512^2
+    images, 384 default tiles) take the half tiles too: every image agrees
+    with one launch per image, and one with the oracle."""
+    probs = [_small(512, 512, 7, synth.MASK_EXPLICIT if b % 2 else synth.MASK_BOUNDARY, seed=500 + b,
+                    blur="gauss", lam=3e-3) for b in range(6)]
+    iters = 12
+    g = gpu_run(probs, iters, check_every=5)
+    a = gpu_run(probs, iters, check_every=5, batched=0)
+    for b in range(len(probs)):
+        assert rel_l2(g["x"][b], a["x"][b]) <= 1e-6, b
+    r = oracle_run(probs[3], iters)
+    assert_parity(g["x"][3], r["x"], what="512^2 in a batch of six, x")
+
+
 def test_one_iteration_full_state(torch_cuda):
     """x^1, ytilde^1, v^1, d^1 after one iteration, per image of a mixed batch."""
     probs = [_small(24, 32, 5, synth.MASK_EXPLICIT, seed=1), _small(48, 36, 7, synth.MASK_DECIMATE, seed=2),
