@@ -144,6 +144,27 @@ def read_traffic(name):
         return None, None
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """GB/s of a plain device-to-device copy of `mib` MiB (read + write
+    counted), best of `reps`, timed with events on the current stream."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / best / 1e9
+
+
 def time_runs(plan, inputs, iters, steps, warmup, backward=False):
     """Seconds for `steps` runs (each: setup, init, all iterations; with
     backward also the reverse pass for a fixed dL/dx), and the wall time."""
@@ -294,9 +315,14 @@ def main():
             kern, avg, ab = "col_kernel", col_avg, cb
         achieved = ab / (avg * 1e-3) / 1e9
         traffic, tk = read_traffic(args.workload)
+        traffic = traffic if (traffic is not None and tk == kern) else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic if (traffic is not None and tk == kern) else None,
+                "traffic": traffic,
+                # measured bytes (counter traffic) over the same launch time
+                "traffic_frac": round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+                # a plain device copy on this GPU: the practical streaming ceiling
+                "copy_gbs": round(copy_bandwidth(), 1),
                 "kernel": kern, "launch_us": round(avg * 1e3, 2), "alg_bytes_per_launch": int(ab),
                 "other_pass": {"kernel": "col_kernel" if kern == "row_kernel" else "row_kernel",
                                "launch_us": round((col_avg if kern == "row_kernel" else row_avg) * 1e3, 2),
