@@ -126,6 +126,12 @@ typedef struct {
                            of a pixel, with lambda and mu of the first channel
                            (pass equal values).  C <= 4; no reverse pass.
                            Default 1. */
+  int32_t spectra_hint; /* cache hint for the spectra the two passes hand each
+                           other: 0 = automatic (non-temporal stores when both
+                           spectrum buffers together take at most 40 MB, i.e.
+                           the working set stays in the last-level cache),
+                           1 = ordinary stores, 2 = non-temporal stores.
+                           Results do not depend on it.  Default 0. */
 } deconv_options;
 
 typedef struct {

@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p), ("bgs_passes", ctypes.c_int32),
                 ("adapt_t", ctypes.c_double), ("warm_iters", ctypes.c_int32),
-                ("warm_tau", ctypes.c_float), ("channels", ctypes.c_int32)]
+                ("warm_tau", ctypes.c_float), ("channels", ctypes.c_int32),
+                ("spectra_hint", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

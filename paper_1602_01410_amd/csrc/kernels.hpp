@@ -150,6 +150,7 @@ struct RowArgs {
   const float* dscale;       // ROW_STATE: per-image factor applied to d, nullable
   float alpha;
   int mode, check, store_v, store_x, last;
+  int nt_spec;               // non-temporal stores of spec_out
 };
 
 struct ColArgs {
@@ -165,6 +166,7 @@ struct ColArgs {
   const int* done;
   int warm;                  // 1: quadratic warm-start solve (|H|^2 + warm_tau)
   float warm_tau;
+  int nt_spec;               // non-temporal stores of spec_out
 };
 
 // x % s == 0 for 0 <= x < 2^11 and 1 < s <= 2^11, with magic = floor(2^32/s) + 1
@@ -232,6 +234,13 @@ template <bool NT>
 __device__ __forceinline__ void st_out(float* p, float v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
+}
+// the spectra one pass leaves for the other: the hint is chosen per plan
+// (it pays when the plan's whole working set stays in the last-level cache)
+template <bool NT_ALWAYS>
+__device__ __forceinline__ void st_spec(float4* p, float4 v, bool nt) {
+  if (NT_ALWAYS || nt) st_out<true>(p, v);
+  else st_out<false>(p, v);
 }
 // The same hint on loads (bits: 1 row-pass state, 2 row-pass spectra, 4
 // column-pass inputs); measured to pay for the row-pass state only.
@@ -382,7 +391,7 @@ __device__ __forceinline__ float row_x(const float2* buf, int l, int nr, int lj)
 // signals a, b and store them in the tiled layout.
 template <int L, int RT>
 __device__ __forceinline__ void split_store(float4* __restrict__ sout, const float2* buf, int M, int r0, int nr,
-                                            int nh, int nb, int C, int logC) {
+                                            int nh, int nb, int C, int logC, bool nt) {
   constexpr int LS = lstride(L);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
   constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
@@ -396,8 +405,9 @@ __device__ __forceinline__ void split_store(float4* __restrict__ sout, const flo
     if (l < nr && blk < nb && kx < nh) {
       const float2 cf = buf[l * LS + lpad(kx)];
       const float2 cm = buf[l * LS + lpad(kx == 0 ? 0 : L - kx)];
-      st_out<kNtRowSpec>(sout + (((__umul24(blk, M) + r0 + l) << logC) + c),
-             make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x)));
+      st_spec<kNtRowSpec>(sout + (((__umul24(blk, M) + r0 + l) << logC) + c),
+             make_float4(0.5f * (cf.x + cm.x), 0.5f * (cf.y - cm.y), 0.5f * (cf.y + cm.y), 0.5f * (cm.x - cf.x)),
+             nt);
     }
   }
 }
@@ -427,7 +437,7 @@ struct PixMap {
 template <int L, int RT, int KP, class Pack>
 __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], int nr, const float2* tw,
                                              float4* __restrict__ sout, int M, int r0, int nh, int nb, int C,
-                                             int logC, Pack pack) {
+                                             int logC, Pack pack, bool nt = false) {
   using PM = PixMap<L>;
   constexpr int LS = lstride(L);
   const unsigned tid = threadIdx.x;
@@ -458,7 +468,7 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
   }
   __syncthreads();
   fft_lines<L, false, kNTR, RT>(buf, nr, tw);
-  split_store<L, RT>(sout, buf, M, r0, nr, nh, nb, C, logC);
+  split_store<L, RT>(sout, buf, M, r0, nr, nh, nb, C, logC, nt);
 }
 
 // One more block-Gauss-Seidel pass of the x- and z-steps with v and d frozen
@@ -700,7 +710,7 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   if (GEN && (a.last || uonly)) return;
   // prologue of the next x-step: pack ytilde + i mu D^T(v - d)
   row_prologue<L, RT, KP>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
-                          [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); });
+                          [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); }, a.nt_spec != 0);
 }
 
 template <int L, int V, int RT = rt_for(L)>
@@ -856,6 +866,7 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
   // output in the row-block layout the row pass reads (runs of rt rows)
   float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rt);
   const unsigned nbc = (unsigned)(mt.nb * C);
+  const bool nt = a.nt_spec != 0;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = threadIdx.x + k * kNTC;
@@ -863,7 +874,8 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
       const int i = q / C, c = q - i * C;
       const float2 X = buf[(2 * c) * LS + lpad(i)];
       const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-      st_out<kNtColSpec>(sout + (row_block_index(mt, i, nbc) + c * mt.rt), make_float4(X.x, X.y, Q.x, Q.y));
+      st_spec<kNtColSpec>(sout + (row_block_index(mt, i, nbc) + c * mt.rt), make_float4(X.x, X.y, Q.x, Q.y),
+                          nt);
     }
   }
 }

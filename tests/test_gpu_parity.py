@@ -296,3 +296,14 @@ def test_long_lengths_one_launch(torch_cuda):
         torch.cuda.synchronize()
     for g1, g2 in zip(*grads):
         assert rel_l2(g2, g1) <= 1e-5
+
+
+def test_spectra_cache_hint_leaves_results_unchanged(torch_cuda):
+    """Ordinary and non-temporal stores of the pass-to-pass spectra give the
+    same bits (the hint only changes where the lines live)."""
+    probs = _mixed(seed0=600)
+    a = gpu_run(probs, 15, spectra_hint=1, check_every=5)
+    b = gpu_run(probs, 15, spectra_hint=2, check_every=5)
+    for i in range(len(probs)):
+        assert np.array_equal(a["x"][i], b["x"][i]), i
+        assert np.array_equal(a["yt"][i], b["yt"][i]), i
