@@ -249,6 +249,7 @@ struct deconv_plan_s {
   const uint8_t* mask = nullptr;  // explicit masks of the last run (caller-owned)
   int cur_d = 0;        // index of the d buffer holding the current state
   bool have_state = false;
+  bool wide_col = false;     // column tiles of kNTCWide threads (few tiles)
   int last_iters = 0;   // iterations of the last run (for the backward)
   bool ck_valid = false;
 
@@ -411,6 +412,13 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     }
     for (int t = 0; t < m.nb; ++t) ct_tiles[b].push_back(TileRef{b, t, (double)m.C * m.m * lc});
   }
+  // Fewer than three column tiles per compute unit: nothing to overlap a
+  // tile's dependent chain with, so twice the threads per tile (one 1024^2
+  // image: column pass 12.4 -> 11.4 us; with many tiles the narrow
+  // workgroups overlap better: 16 x 1024^2, 77 -> 83 us if widened).
+  long long ncol = 0;
+  for (int b = 0; b < B; ++b) ncol += (long long)ct_tiles[b].size();
+  p->wide_col = ncol < 3LL * num_cus();
   size_t rlds = 0, clds = 0;
   const int grt = half ? rt_half(*widths.begin()) : 0;
   for (int w : widths) rlds = std::max(rlds, row_lds_bytes(w, grt));
@@ -856,7 +864,8 @@ static deconv_status launch_cols(deconv_plan_s* p, ColArgs a) {
   const std::vector<Group>& gs = p->opt.batched ? p->col_groups : pass_groups(p, false);
   for (size_t k = 0; k < gs.size(); ++k) {
     a.tiles = p->d_tiles + gs[k].tile0;
-    HIPCHK(launch_col(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size())));
+    HIPCHK(launch_col(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size()),
+                      p->wide_col && has_wide_col(gs[k].L)));
   }
   timer.done();
   return DECONV_OK;

@@ -50,6 +50,7 @@ namespace dcv {
 constexpr int kNT = DCV_NT;       // threads per workgroup of the setup / reduction kernels
 constexpr int kNTR = DCV_NT_ROW;  // threads per workgroup of the row passes
 constexpr int kNTC = DCV_NT_COL;  // threads per workgroup of the column passes
+constexpr int kNTCWide = 512;     // column workgroups of plans with few tiles
 
 // rows per row-pass tile (about DCV_ROW_PIX pixels, at least 2 rows) and
 // columns per column-pass block (a power of two, about DCV_COL_ELEMS / L)
@@ -777,20 +778,20 @@ __global__ void __launch_bounds__(kNTR, DCV_MULTI_ROW_WAVES) row_kernel_multi(Ro
 // ---------------------------------------------------------------------------
 // Registers of one column tile between its loads and its use: the (Y, mu G)
 // column spectra, the blur spectrum and the |D|^2 sums of its frequencies.
-template <int L>
+template <int L, int NT = kNTC>
 struct ColLoad {
   static constexpr int C = c_for(L);
-  static constexpr int NQ = (L * C + kNTC - 1) / kNTC;
+  static constexpr int NQ = (L * C + NT - 1) / NT;
   float4 g[NQ];
   float2 Hk[NQ];
   float dsum[NQ];
 };
 
 // issue every load of tile (img, blk)
-template <int L>
-__device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, int blk, ColLoad<L>& r) {
+template <int L, int NT>
+__device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, int blk, ColLoad<L, NT>& r) {
   constexpr int C = c_for(L);
-  constexpr int NQ = ColLoad<L>::NQ;
+  constexpr int NQ = ColLoad<L, NT>::NQ;
   const long long base = mt.sp + (long long)blk * L * C;
   const float4* __restrict__ sin = a.spec_in + base;
   const float2* __restrict__ hh = a.hh + mt.hh + (long long)blk * L * C;
@@ -798,7 +799,7 @@ __device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, in
   const float* __restrict__ dh2 = dv2 + L;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const int q = threadIdx.x + k * kNTC;
+    const int q = threadIdx.x + k * NT;
     if (q < L * C) {
       const int ky = q / C, c = q - ky * C;
       r.g[k] = ld_in<kNtLdCol>(sin + q);
@@ -809,13 +810,13 @@ __device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, in
 }
 
 // the column spectra into the LDS lines (Y in line 2c, mu G in line 2c+1)
-template <int L>
-__device__ __forceinline__ void col_fill(const ColLoad<L>& r, float2* buf) {
+template <int L, int NT>
+__device__ __forceinline__ void col_fill(const ColLoad<L, NT>& r, float2* buf) {
   constexpr int C = c_for(L);
   constexpr int LS = lstride(L);
 #pragma unroll
-  for (int k = 0; k < ColLoad<L>::NQ; ++k) {
-    const int q = threadIdx.x + k * kNTC;
+  for (int k = 0; k < ColLoad<L, NT>::NQ; ++k) {
+    const int q = threadIdx.x + k * NT;
     if (q < L * C) {
       const int i = q / C, c = q - i * C;
       buf[(2 * c) * LS + lpad(i)] = make_float2(r.g[k].x, r.g[k].y);
@@ -826,19 +827,19 @@ __device__ __forceinline__ void col_fill(const ColLoad<L>& r, float2* buf) {
 
 // forward column DFTs, x-step solve, Q = H X, inverse DFTs, store (X, Q);
 // the caller has filled the lines (not yet synchronised)
-template <int L>
+template <int L, int NT>
 __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta& mt, int blk, float muv,
                                                 const float2* Hk, const float* dsum, float2* buf, const float2* tw) {
   constexpr int C = c_for(L);
   constexpr int LS = lstride(L);
-  constexpr int NQ = ColLoad<L>::NQ;
+  constexpr int NQ = ColLoad<L, NT>::NQ;
   const long long base = mt.sp + (long long)blk * L * C;
   __syncthreads();
-  fft_lines<L, false, kNTC, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, false, NT, 2 * C>(buf, 2 * C, tw);
   const float scale = 1.0f / ((float)L * (float)mt.n);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const int q = threadIdx.x + k * kNTC;
+    const int q = threadIdx.x + k * NT;
     if (q < L * C) {
       const int ky = q / C, c = q - ky * C;
       const int kx = blk * C + c;
@@ -862,14 +863,14 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
     }
   }
   __syncthreads();
-  fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, true, NT, 2 * C>(buf, 2 * C, tw);
   // output in the row-block layout the row pass reads (runs of rt rows)
   float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rt);
   const unsigned nbc = (unsigned)(mt.nb * C);
   const bool nt = a.nt_spec != 0;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const int q = threadIdx.x + k * kNTC;
+    const int q = threadIdx.x + k * NT;
     if (q < L * C) {
       const int i = q / C, c = q - i * C;
       const float2 X = buf[(2 * c) * LS + lpad(i)];
@@ -880,24 +881,26 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
   }
 }
 
-template <int L>
+// NT threads per tile: kNTC, or kNTCWide for plans with few tiles (a shorter
+// dependent chain per tile when a compute unit has no other tile to overlap)
+template <int L, int NT = kNTC>
 __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, float2* lds) {
   constexpr int C = c_for(L);
   const ImgMeta mt = a.meta[img];
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTC>(lds + 2 * C * lstride(L), a.tw + mt.twc);
-  ColLoad<L> r;
-  col_load<L>(a, mt, blk, r);
-  col_fill<L>(r, buf);
-  col_solve_store<L>(a, mt, blk, a.mu[img], r.Hk, r.dsum, buf, tw);
+  const float2* tw = twiddle_table<L, NT>(lds + 2 * C * lstride(L), a.tw + mt.twc);
+  ColLoad<L, NT> r;
+  col_load<L, NT>(a, mt, blk, r);
+  col_fill<L, NT>(r, buf);
+  col_solve_store<L, NT>(a, mt, blk, a.mu[img], r.Hk, r.dsum, buf, tw);
 }
 
-template <int L>
-__global__ void __launch_bounds__(kNTC) col_kernel(ColArgs a) {
+template <int L, int NT = kNTC>
+__global__ void __launch_bounds__(NT) col_kernel(ColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  col_tile<L>(a, t.x, t.y, lds);
+  col_tile<L, NT>(a, t.x, t.y, lds);
 }
 
 template <int L0, int... Ls>

@@ -87,8 +87,19 @@ extern template hipError_t launch_row_variant<RV_CHECK>(int, int, int, size_t, h
                                                         hipEvent_t);
 extern template hipError_t launch_row_variant<RV_GENERIC>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
                                                           hipEvent_t);
+// wide: kNTCWide threads per column tile where the length has that
+// instantiation (has_wide_col), for plans with few tiles
+#define DCV_FOR_EACH_WIDE_COL_LEN(X) X(512) X(576) X(768) X(1024) X(1152) X(1536) X(2048)
+inline bool has_wide_col(int L) {
+  switch (L) {
+#define DCV_CASE(n) case n: return true;
+    DCV_FOR_EACH_WIDE_COL_LEN(DCV_CASE)
+#undef DCV_CASE
+  }
+  return false;
+}
 hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr);
+                      hipEvent_t e1 = nullptr, bool wide = false);
 hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a);
 hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a);
 
