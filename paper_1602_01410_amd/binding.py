@@ -227,6 +227,9 @@ class Plan:
         return tuple(out)
 
     def state_import(self, mask, h, yt, v, d):
+        """Load a resumable state (ytilde, v, d as packed device tensors, v and d
+        interleaved per pixel) so that `cont` continues from it; `mask` is
+        the packed byte mask (None when every image's mask is implicit)."""
         _check(lib().deconv_state_import(self.handle, _ptr(mask), _ptr(h), _ptr(yt), _ptr(v), _ptr(d)),
                "state_import")
 
