@@ -158,3 +158,41 @@ def test_early_stop_on_residuals():
             h = r["hist"][-1]
             assert h[0] <= 2e-4 * sc * 1.01 and h[1] <= 2e-4 * sc * 1.01
     assert stopped >= 1
+
+
+@pytest.mark.timeout(400)
+def test_batch_with_buffers_beyond_4gib():
+    """136 images of 2048^2 in one plan (570 Mpx: the pixel-pair and spectrum
+    buffers pass 4 GiB, so every 64-bit offset path is used): the first,
+    a middle and the last image come out bit for bit as from a plan of that
+    image alone, whose tiles are the same."""
+    import torch
+    from paper_1602_01410_amd import binding
+    B, iters = 136, 4
+    p = synth.problem(2048, 2048, 9, "rect", "gauss", sigma=1.5, bsnr=45.0, lam=1e-3, mu=0.05, seed=2048,
+                      nrect=20)
+    y1 = torch.from_numpy(p["y"].reshape(-1)).cuda()
+    h1 = torch.from_numpy(p["h"].reshape(-1)).cuda()
+    # each image scaled differently so that a mix-up between images shows
+    scale = torch.arange(1, B + 1, dtype=torch.float32, device="cuda") / B
+    y = (y1[None, :] * scale[:, None]).reshape(-1).contiguous()
+    h = h1.repeat(B)
+    lam = torch.full((B,), 1e-3, dtype=torch.float32, device="cuda")
+    mu = torch.full((B,), 0.05, dtype=torch.float32, device="cuda")
+    log("%d x 2048^2: %.2f GiB per float2 pixel buffer" % (B, y.numel() * 8 / 2 ** 30))
+    plan = binding.Plan([desc(p)] * B, check_every=2)
+    x, st = plan.run(y, None, h, lam, mu, iters, stats=True)
+    torch.cuda.synchronize()
+    n = 2048 * 2048
+    picks = [0, B // 2, B - 1]
+    xb = {b: x[b * n:(b + 1) * n].cpu() for b in picks}
+    assert all(s["status"] == 0 and s["iters_done"] == iters for s in st)
+    del x, plan
+    torch.cuda.empty_cache()
+    for b in picks:
+        one = binding.Plan([desc(p)], check_every=2)
+        xo, _ = one.run(y[b * n:(b + 1) * n].contiguous(), None, h1, lam[:1], mu[:1], iters)
+        torch.cuda.synchronize()
+        log("image %d: max |diff| %.3e" % (b, float((xo.cpu() - xb[b]).abs().max())))
+        assert torch.equal(xo.cpu(), xb[b]), b
+        one.close()
