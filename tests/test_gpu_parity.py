@@ -233,6 +233,19 @@ def test_error_paths(torch_cuda):
     with pytest.raises(binding.DeconvError) as e:
         binding.Plan([dict(height=64, width=64, ksize=4)])
     assert e.value.code == 2
+    # no iterations, and continuing a plan that never ran
+    with pytest.raises(binding.DeconvError) as e:
+        plan.run(y, mask, h, lam, mu, 0)
+    assert e.value.code == 1
+    fresh = binding.Plan([desc(p)])
+    with pytest.raises(binding.DeconvError) as e:
+        fresh.cont(lam, mu, 3, torch.empty_like(y))
+    with pytest.raises(binding.DeconvError):
+        fresh.state_export(y.device)
+    # the plan still runs normally after the refused calls
+    x, st = plan.run(y, mask, h, lam, mu, 4, stats=True)
+    torch.cuda.synchronize()
+    assert st[0]["status"] == 0 and bool(torch.isfinite(x).all())
 
 
 def test_autotuned_schedules_agree(tmp_path):
