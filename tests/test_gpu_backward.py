@@ -69,3 +69,30 @@ def test_autograd_function():
                                       (x.detach().cpu().numpy() - p["x_true"].reshape(-1)).reshape(p["M"], p["N"]))
     assert rel_l2(y.grad.cpu().numpy().reshape(p["M"], p["N"]), ry) <= 1e-3
     assert rel_l2(h.grad.cpu().numpy().reshape(p["K"], p["K"]), rh) <= 1e-3
+
+
+def test_backward_few_tiles_matches_batch():
+    """A lone 512^2 image takes the launch choices of plans with few tiles
+    (512-thread column tiles, non-temporal spectra) in its forward recompute;
+    its gradients equal those of the same image inside a batch of eight,
+    which takes the ordinary ones."""
+    import torch
+    from paper_1602_01410_amd import binding
+    p = synth.problem(512, 512, 9, "rect", "gauss", sigma=1.5, bsnr=45.0, lam=1e-3, mu=0.05, seed=512, nrect=12)
+    iters, ck = 10, 5
+    out = []
+    for B in (1, 8):
+        probs = [p] * B
+        plan = binding.Plan([desc(q) for q in probs], ckpt_every=ck, max_iters=iters)
+        y, mask, h, lam, mu = device_inputs(probs)
+        plan.run(y, mask, h, lam, mu, iters)
+        n = 512 * 512
+        # the same dL/dx on every image
+        gx = torch.sin((torch.arange(y.numel(), device=y.device) % n).float() * 1e-3).contiguous()
+        gy, gl, gh = plan.backward(y, mask, h, lam, mu, gx)
+        torch.cuda.synchronize()
+        out.append((gy[:n].cpu().numpy().astype(np.float64), float(gl[0]), gh[:81].cpu().numpy().astype(np.float64)))
+        plan.close()
+    (y1, l1, h1), (y8, l8, h8) = out
+    log("grad_y %.2e grad_h %.2e grad_lambda %.2e" % (rel_l2(y8, y1), rel_l2(h8, h1), abs(l8 - l1) / abs(l1)))
+    assert rel_l2(y8, y1) <= 1e-6 and rel_l2(h8, h1) <= 1e-6 and abs(l8 - l1) <= 1e-6 * abs(l1)
