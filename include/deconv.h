@@ -177,7 +177,8 @@ deconv_status deconv_plan_destroy(deconv_plan p);
  *   x_out  device float, packed: x^iters on the whole extended domain
  *   ytilde_out  device float, packed, nullable: [y; z] after the last z-step
  *   stats  host array [batch], nullable; when given the call synchronises
- *          and fills it.
+ *          and fills it.  An image whose status is DECONV_ERR_NONFINITE
+ *          stopped early and its x_out is unspecified.
  * The state (ytilde, v, d) stays in the plan for deconv_admm_continue,
  * deconv_state_export and, with checkpoints, deconv_admm_backward.
  */

@@ -1013,10 +1013,12 @@ static IterFlags flags_for(const deconv_plan_s* p, int it, int iters) {
   IterFlags f{};
   f.last = it == iters - 1;
   f.check = K > 0 && ((it + 1) % K == 0);
-  // v is kept for the next check (it reads v^i) and at every check, so that
-  // an image stopped there leaves a consistent state (v, d of that iteration)
-  f.store_v = f.last || f.check || (K > 0 && (K == 1 || ((it + 2) % K == 0)));
-  f.store_x = f.last || f.check;
+  // v is kept for the next check (it reads v^i); with tolerances, an image
+  // may stop at any check, so every check also stores v and x to leave the
+  // state of that iteration.  Without them only the last iteration stores x.
+  const bool may_stop = f.check && (p->opt.tol_primal > 0 || p->opt.tol_dual > 0);
+  f.store_v = f.last || may_stop || (K > 0 && (K == 1 || ((it + 2) % K == 0)));
+  f.store_x = f.last || may_stop;
   return f;
 }
 

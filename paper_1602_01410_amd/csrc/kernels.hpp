@@ -562,7 +562,8 @@ __device__ __forceinline__ float vsoft_scale(float n2, float tau, float tau2) {
 //   RV_PLAIN   ROW_ITER, no residuals, no stores of v, x or u (most
 //              iterations between two residual checks);
 //   RV_STOREV  ROW_ITER storing v only (the iteration before a check);
-//   RV_CHECK   ROW_ITER with residuals and stores of v and x (a check);
+//   RV_CHECK   ROW_ITER with residuals (a check), storing v and x as the
+//              arguments ask (only where the run may stop there);
 //   RV_GENERIC every mode and flag from the arguments.
 enum { RV_PLAIN = 0, RV_STOREV = 1, RV_CHECK = 2, RV_GENERIC = 3 };
 
@@ -571,7 +572,7 @@ __host__ __device__ inline int row_variant(const RowArgs& a) {
   if (a.mode != ROW_ITER || a.u_out || a.last) return RV_GENERIC;
   if (!a.check && !a.store_v && !a.store_x) return RV_PLAIN;
   if (!a.check && a.store_v && !a.store_x) return RV_STOREV;
-  if (a.check && a.store_v && a.store_x) return RV_CHECK;
+  if (a.check) return RV_CHECK;
   return RV_GENERIC;
 }
 
@@ -590,8 +591,8 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   const bool check = V == RV_CHECK || (GEN && a.check);
   const bool uonly = GEN && a.mode == ROW_UONLY;
-  const bool store_v = V == RV_STOREV || V == RV_CHECK || (GEN && a.store_v);
-  const bool store_x = V == RV_CHECK || (GEN && a.store_x);
+  const bool store_v = V == RV_STOREV || ((V == RV_CHECK || GEN) && a.store_v);
+  const bool store_x = (V == RV_CHECK || GEN) && a.store_x;
   // image-local bases (uniform) with 32-bit offsets below
   const float2* __restrict__ d_in = a.d_in + mt.px;
   float2* __restrict__ d_out = a.d_out + mt.px;
