@@ -121,7 +121,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   float sz[KP];
   unsigned obsbits = 0;
   if (!start) {
-    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
 #if !DCV_BWD_EARLY_STATE
     // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
     __syncthreads();
@@ -310,13 +310,13 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
   }
   __syncthreads();
   fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
-  float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rt);
+  float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rb);
   const unsigned nbc = (unsigned)(mt.nb * C);
   for (int q = threadIdx.x; q < L * C; q += kNTC) {
     const int i = q / C, c = q - i * C;
     const float2 X = buf[(2 * c) * LS + lpad(i)];
     const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-    sout[row_block_index(mt, i, nbc) + c * mt.rt] = make_float4(X.x, X.y, Q.x, Q.y);
+    sout[row_block_index(mt, i, nbc) + c * mt.rb] = make_float4(X.x, X.y, Q.x, Q.y);
   }
 }
 

@@ -375,6 +375,11 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     m.rt = half ? rt_half(d.width) : rt_for(d.width);
     m.nrt = (d.height + m.rt - 1) / m.rt;
     m.rtmagic = m.rt > 1 ? (unsigned)((1ull << 32) / (unsigned)m.rt) + 1u : 0u;
+    // the spectra the column pass leaves for the row pass come in row blocks
+    // of rb rows (longer contiguous runs for its stores), rb a multiple of
+    // the row tile height
+    m.rb = rt_for(d.width) * DCV_ROW_BLOCK_MULT;
+    m.rbmagic = m.rb > 1 ? (unsigned)((1ull << 32) / (unsigned)m.rb) + 1u : 0u;
     m.px = px; m.sp = sp; m.hh = hhp; m.tab = tab; m.rt0 = rt;
     m.nch = std::max(1, p->opt.channels);
     m.group = b - b % m.nch;
@@ -383,8 +388,9 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     m.twr = twoff[d.width]; m.twc = twoff[d.height];
     p->hoff_h[b] = hk;
     px += (long long)d.height * d.width;
-    // spectra: whole row tiles (the row-block layout pads the last one)
-    sp += (long long)m.nrt * m.rt * m.nb * m.C;
+    // spectra: whole row blocks (the row-block layout pads the last one)
+    sp += (long long)std::max((long long)m.nrt * m.rt, (long long)((d.height + m.rb - 1) / m.rb) * m.rb) *
+          m.nb * m.C;
     hhp += (long long)d.height * m.nb * m.C;
     tab += d.height + m.nb * m.C;
     rt += m.nrt;

@@ -57,6 +57,11 @@ constexpr int kNTCWide = 512;     // column workgroups of plans with few tiles
 __host__ __device__ constexpr int rt_for(int L) {
   return DCV_ROW_PIX / L < 2 ? 2 : (DCV_ROW_PIX / L > 32 ? 32 : DCV_ROW_PIX / L);
 }
+// rows per block of the row-block spectrum layout, in units of the default
+// row tile height
+#ifndef DCV_ROW_BLOCK_MULT
+#define DCV_ROW_BLOCK_MULT 1
+#endif
 __host__ __device__ constexpr int c_for(int L) {
   int c = 1;
   while (c * 2 <= DCV_COL_ELEMS / L && c * 2 <= 16) c *= 2;
@@ -121,6 +126,8 @@ struct ImgMeta {
   unsigned rtmagic;    // floor(2^32 / rt) + 1 (rt > 1): exact i / rt for rows i < 2^11
   int group;           // first image of the colour group (itself for grey images)
   int nch;             // channels of the group (1 for grey images)
+  int rb;              // rows per block of the row-block spectrum layout (a multiple of rt)
+  unsigned rbmagic;    // floor(2^32 / rb) + 1 (rb > 1): exact i / rb for rows i < 2^11
 };
 
 // ROW_ITER: finish an iteration (z-step, prox, dual update) and start the
@@ -178,9 +185,9 @@ __device__ __forceinline__ bool divisible(int x, int s, unsigned magic) {
 
 // offset of entry (row i, column 0 of the block) in the row-block layout of
 // the spectra the column pass writes for the row pass (entry (i, kx) at
-// (i / rt) rt nbc + kx rt + i mod rt; the caller adds (kx - blk C) rt)
+// (i / rb) rb nbc + kx rb + i mod rb; the caller adds (kx - blk C) rb)
 __device__ __forceinline__ unsigned row_block_index(const ImgMeta& mt, int i, unsigned nbc) {
-  const unsigned i0 = mt.rt == 1 ? (unsigned)i : __umulhi((unsigned)i, mt.rtmagic) * (unsigned)mt.rt;
+  const unsigned i0 = mt.rb == 1 ? (unsigned)i : __umulhi((unsigned)i, mt.rbmagic) * (unsigned)mt.rb;
   return i0 * nbc + (unsigned)(i - (int)i0);
 }
 
@@ -318,11 +325,12 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // Gather the tile's half spectra into those lines, completing the other
 // half by Hermitian symmetry: X + iQ for the own rows, X(r0-1) + i X(r0+nr)
 // for the halo line.  The column pass leaves the spectra in row blocks of
-// RT rows (entry (i, kx) at (i / RT) RT nbc + kx RT + i mod RT, nbc = nb C):
-// the own rows are one contiguous block.  All loads are issued first.
+// rb rows (entry (i, kx) at (i / rb) rb nbc + kx rb + i mod rb, nbc = nb C),
+// rb a multiple of RT: the own rows are RT consecutive rows of one block (the
+// whole block when rb = RT).  All loads are issued first.
 template <int L, int RT, bool HALO = true>
 __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
-                                            int nh, int nb, int C, int logC) {
+                                            int nh, int nb, int C, int logC, int rb) {
   constexpr int LS = lstride(L);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
   constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
@@ -333,26 +341,30 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   float2 ha[NH], hb[NH];
   const int ia = r0 == 0 ? M - 1 : r0 - 1;
   const int ib = r0 + nr == M ? 0 : r0 + nr;
-  // the tile's block: entry (r0 + l, kx) at r0 nbc + kx RT + l
+  // the tile's rows in their block: entry (r0 + l, kx) at
+  // (r0 / rb) rb nbc + r0 mod rb + kx rb + l
   const unsigned nbc = (unsigned)(nb * C);
-  const float4* __restrict__ blkp = sin + (unsigned)r0 * nbc;
+  const unsigned rbu = (unsigned)rb;
+  const unsigned b0 = (unsigned)(r0 / rb) * rbu;
+  const float4* __restrict__ blkp = sin + (b0 * nbc + ((unsigned)r0 - b0));
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = threadIdx.x + k * kNTR;
     const int l = q % RT, kx = q / RT;
     dst[k] = -1;
     if (l < nr && kx < nh) {
-      g[k] = ld_in<kNtLdRowSpec>(blkp + q);
+      g[k] = ld_in<kNtLdRowSpec>(blkp + ((unsigned)kx * rbu + (unsigned)l));
       dst[k] = l * LS + kx;
     }
   }
-  const unsigned ba = (unsigned)(ia / RT) * RT * nbc + ia % RT, bb = (unsigned)(ib / RT) * RT * nbc + ib % RT;
+  const unsigned ba = (unsigned)(ia / rb) * rbu * nbc + (unsigned)(ia % rb);
+  const unsigned bb = (unsigned)(ib / rb) * rbu * nbc + (unsigned)(ib % rb);
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
     const int kx = threadIdx.x + k * kNTR;
     if (HALO && kx < nh) {
-      ha[k] = sin2[2 * (ba + (unsigned)kx * RT)];
-      hb[k] = sin2[2 * (bb + (unsigned)kx * RT)];
+      ha[k] = sin2[2 * (ba + (unsigned)kx * rbu)];
+      hb[k] = sin2[2 * (bb + (unsigned)kx * rbu)];
     }
   }
 #pragma unroll
@@ -493,7 +505,7 @@ __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, i
   float* __restrict__ yt = a.yt + mt.px;
   float2* buf = lds;
   const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
-  gather_rows<L, RT, false>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+  gather_rows<L, RT, false>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
   float yo[KP];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -611,7 +623,7 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
   if (!GEN || a.mode == ROW_ITER || uonly) {
-    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC);
+    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
     __syncthreads();
 #if DCV_EARLY_STATE
     // state loads for the epilogue, issued before the transform
@@ -866,7 +878,7 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
   __syncthreads();
   fft_lines<L, true, NT, 2 * C>(buf, 2 * C, tw);
   // output in the row-block layout the row pass reads (runs of rt rows)
-  float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rt);
+  float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rb);
   const unsigned nbc = (unsigned)(mt.nb * C);
   const bool nt = a.nt_spec != 0;
 #pragma unroll
@@ -876,7 +888,7 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
       const int i = q / C, c = q - i * C;
       const float2 X = buf[(2 * c) * LS + lpad(i)];
       const float2 Q = buf[(2 * c + 1) * LS + lpad(i)];
-      st_spec<kNtColSpec>(sout + (row_block_index(mt, i, nbc) + c * mt.rt), make_float4(X.x, X.y, Q.x, Q.y),
+      st_spec<kNtColSpec>(sout + (row_block_index(mt, i, nbc) + c * mt.rb), make_float4(X.x, X.y, Q.x, Q.y),
                           nt);
     }
   }
