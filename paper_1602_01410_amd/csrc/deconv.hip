@@ -250,6 +250,7 @@ struct deconv_plan_s {
   int cur_d = 0;        // index of the d buffer holding the current state
   bool have_state = false;
   bool wide_col = false;     // column tiles of kNTCWide threads (few tiles)
+  bool wide_row = false;     // half-height row tiles of kNTRWide threads (few tiles)
   int last_iters = 0;   // iterations of the last run (for the backward)
   bool ck_valid = false;
 
@@ -396,6 +397,10 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     rt += m.nrt;
     hk += (long long)d.ksize * d.ksize;
   }
+  // Half-height tiles fewer than three per compute unit (one 1024^2 image:
+  // 512) run with 1024 threads: a shorter dependent chain per tile (row pass
+  // 16.7 -> 15.7 us); batches lose 5-10% that way.
+  p->wide_row = half && rt < 3LL * num_cus();
   p->total_px = px; p->total_sp = sp; p->total_hh = hhp; p->total_tab = tab; p->total_tw = tw;
   p->total_rt = rt; p->total_h = hk; p->tw_off = twoff;
 
@@ -859,7 +864,7 @@ static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
   for (size_t k = 0; k < gs.size(); ++k) {
     a.tiles = p->d_tiles + gs[k].tile0;
     HIPCHK(launch_row(gs[k].L, gs[k].rt, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k),
-                      timer.stop(k, gs.size())));
+                      timer.stop(k, gs.size()), p->wide_row));
   }
   timer.done();
   return DECONV_OK;

@@ -49,6 +49,7 @@ namespace dcv {
 #endif
 constexpr int kNT = DCV_NT;       // threads per workgroup of the setup / reduction kernels
 constexpr int kNTR = DCV_NT_ROW;  // threads per workgroup of the row passes
+constexpr int kNTRWide = 1024;    // row workgroups of plans with few tiles
 constexpr int kNTC = DCV_NT_COL;  // threads per workgroup of the column passes
 constexpr int kNTCWide = 512;     // column workgroups of plans with few tiles
 
@@ -328,13 +329,13 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // rb rows (entry (i, kx) at (i / rb) rb nbc + kx rb + i mod rb, nbc = nb C),
 // rb a multiple of RT: the own rows are RT consecutive rows of one block (the
 // whole block when rb = RT).  All loads are issued first.
-template <int L, int RT, bool HALO = true>
+template <int L, int RT, bool HALO = true, int NT = kNTR>
 __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC, int rb) {
   constexpr int LS = lstride(L);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
-  constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
-  constexpr int NH = (NBC_MAX + kNTR - 1) / kNTR;
+  constexpr int NQ = (RT * NBC_MAX + NT - 1) / NT;
+  constexpr int NH = (NBC_MAX + NT - 1) / NT;
   const float2* __restrict__ sin2 = reinterpret_cast<const float2*>(sin);
   float4 g[NQ];
   int dst[NQ];
@@ -349,7 +350,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   const float4* __restrict__ blkp = sin + (b0 * nbc + ((unsigned)r0 - b0));
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const int q = threadIdx.x + k * kNTR;
+    const int q = threadIdx.x + k * NT;
     const int l = q % RT, kx = q / RT;
     dst[k] = -1;
     if (l < nr && kx < nh) {
@@ -361,7 +362,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   const unsigned bb = (unsigned)(ib / rb) * rbu * nbc + (unsigned)(ib % rb);
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const int kx = threadIdx.x + k * kNTR;
+    const int kx = threadIdx.x + k * NT;
     if (HALO && kx < nh) {
       ha[k] = sin2[2 * (ba + (unsigned)kx * rbu)];
       hb[k] = sin2[2 * (bb + (unsigned)kx * rbu)];
@@ -380,7 +381,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   float2* hline = buf + nr * LS;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const int kx = threadIdx.x + k * kNTR;
+    const int kx = threadIdx.x + k * NT;
     if (HALO && kx < nh) {
       hline[lpad(kx)] = make_float2(ha[k].x - hb[k].y, ha[k].y + hb[k].x);
       if (kx >= 1 && kx <= L - nh) hline[lpad(L - kx)] = make_float2(ha[k].x + hb[k].y, hb[k].x - ha[k].y);
@@ -402,15 +403,15 @@ __device__ __forceinline__ float row_x(const float2* buf, int l, int nr, int lj)
 
 // Split C = F(a) + i F(b) of lines 0..nr-1 into the half spectra of the real
 // signals a, b and store them in the tiled layout.
-template <int L, int RT>
+template <int L, int RT, int NT = kNTR>
 __device__ __forceinline__ void split_store(float4* __restrict__ sout, const float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC, bool nt) {
   constexpr int LS = lstride(L);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
-  constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
+  constexpr int NQ = (RT * NBC_MAX + NT - 1) / NT;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const int q = threadIdx.x + k * kNTR;
+    const int q = threadIdx.x + k * NT;
     const int c = q & (C - 1);
     const int t2 = q >> logC;
     const int l = t2 % RT, blk = t2 / RT;
@@ -428,33 +429,33 @@ __device__ __forceinline__ void split_store(float4* __restrict__ sout, const flo
 // Pixel p = tid + k * kNTR of a row tile sits on tile row p / L, column p % L.
 // When L is a multiple of the workgroup size the row is a compile-time
 // function of k; when the workgroup covers whole rows it is a shift.
-template <int L>
+template <int L, int NT = kNTR>
 struct PixMap {
-  static constexpr bool kSplitRow = L % kNTR == 0;
-  static constexpr bool kWholeRows = !kSplitRow && kNTR % L == 0;
+  static constexpr bool kSplitRow = L % NT == 0;
+  static constexpr bool kWholeRows = !kSplitRow && NT % L == 0;
   __device__ static __forceinline__ int row(int k, unsigned tid) {
-    if constexpr (kSplitRow) return k / (L / kNTR);
-    else if constexpr (kWholeRows) return k * (kNTR / L) + (int)(tid / L);
-    else return (int)((tid + k * kNTR) / L);
+    if constexpr (kSplitRow) return k / (L / NT);
+    else if constexpr (kWholeRows) return k * (NT / L) + (int)(tid / L);
+    else return (int)((tid + k * NT) / L);
   }
   __device__ static __forceinline__ int col(int k, unsigned tid) {
-    if constexpr (kSplitRow) return (k % (L / kNTR)) * kNTR + (int)tid;
+    if constexpr (kSplitRow) return (k % (L / NT)) * NT + (int)tid;
     else if constexpr (kWholeRows) return (int)(tid % L);
-    else return (int)((tid + k * kNTR) % L);
+    else return (int)((tid + k * NT) % L);
   }
 };
 
 // Start of the next transform: with a vector field w of tile rows 0..nr in
 // wreg, form g = D^T w on the own rows, pack(k, l, j, g) into the own lines,
 // transform them forward and store their split half spectra.
-template <int L, int RT, int KP, class Pack>
+template <int L, int RT, int KP, int NT = kNTR, class Pack>
 __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], int nr, const float2* tw,
                                              float4* __restrict__ sout, int M, int r0, int nh, int nb, int C,
                                              int logC, Pack pack, bool nt = false) {
-  using PM = PixMap<L>;
+  using PM = PixMap<L, NT>;
   constexpr int LS = lstride(L);
   const unsigned tid = threadIdx.x;
-  __builtin_assume(tid < (unsigned)kNTR);
+  __builtin_assume(tid < (unsigned)NT);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -480,8 +481,8 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
     if (l <= nr && l >= 1) buf[(l - 1) * LS + lpad(j)] = wreg[k];
   }
   __syncthreads();
-  fft_lines<L, false, kNTR, RT>(buf, nr, tw);
-  split_store<L, RT>(sout, buf, M, r0, nr, nh, nb, C, logC, nt);
+  fft_lines<L, false, NT, RT>(buf, nr, tw);
+  split_store<L, RT, NT>(sout, buf, M, r0, nr, nh, nb, C, logC, nt);
 }
 
 // One more block-Gauss-Seidel pass of the x- and z-steps with v and d frozen
@@ -590,14 +591,14 @@ __host__ __device__ inline int row_variant(const RowArgs& a) {
 
 // One row tile of nr <= RT own rows (nr == RT is passed as a literal for the
 // full tiles, so that their row bounds fold away).
-template <int L, int V, int RT>
+template <int L, int V, int RT, int NT = kNTR>
 __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& mt, int img, int r0, int nr,
                                               float2* lds) {
-  using PM = PixMap<L>;
+  using PM = PixMap<L, NT>;
   constexpr int LS = lstride(L);
-  constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;  // pixels per thread (own rows + 1 halo)
+  constexpr int KP = ((RT + 1) * L + NT - 1) / NT;  // pixels per thread (own rows + 1 halo)
   const unsigned tid = threadIdx.x;
-  __builtin_assume(tid < (unsigned)kNTR);
+  __builtin_assume(tid < (unsigned)NT);
   constexpr bool GEN = V == RV_GENERIC;
   const int M = mt.m;
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
@@ -613,7 +614,7 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   float* __restrict__ x_out = store_x ? a.x_out + mt.px : nullptr;
   float2* __restrict__ u_out = (GEN && a.u_out) ? a.u_out + mt.px : nullptr;
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
+  const float2* tw = twiddle_table<L, NT>(lds + (RT + 1) * LS, a.tw + mt.twr);
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
   const float tau2 = tau * tau;
@@ -623,7 +624,7 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
   if (!GEN || a.mode == ROW_ITER || uonly) {
-    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
+    gather_rows<L, RT, true, NT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
     __syncthreads();
 #if DCV_EARLY_STATE
     // state loads for the epilogue, issued before the transform
@@ -638,9 +639,9 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
         if (l >= 1) yo[k] = ld_in<kNtLdRowState>(yt + pix);
       }
     }
-    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+    fft_lines<L, true, NT, RT + 1>(buf, nr + 1, tw);
 #else
-    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+    fft_lines<L, true, NT, RT + 1>(buf, nr + 1, tw);
     float2 dd[KP];
     float yo[KP];
 #pragma unroll
@@ -713,7 +714,7 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   }
 
   if (check) {
-    __shared__ double red[3 * (kNTR / 64)];
+    __shared__ double red[3 * (NT / 64)];
     double rdd = rd, rvd = rv, rzd = rz;
     block_sum3(rdd, rvd, rzd, red);
     if (threadIdx.x == 0) {
@@ -723,16 +724,18 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   }
   if (GEN && (a.last || uonly)) return;
   // prologue of the next x-step: pack ytilde + i mu D^T(v - d)
-  row_prologue<L, RT, KP>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
+  row_prologue<L, RT, KP, NT>(buf, wreg, nr, tw, a.spec_out + mt.sp, M, r0, nh, nb, C, logC,
                           [&](int k, int, int, float g) { return make_float2(ynew[k], mu * g); }, a.nt_spec != 0);
 }
 
-template <int L, int V, int RT = rt_for(L)>
+template <int L, int V, int RT = rt_for(L), int NT = kNTR>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, float2* lds) {
   const ImgMeta mt = a.meta[img];
-  if (V == RV_GENERIC && a.mode == ROW_INNER) {
-    row_inner<L, RT>(a, mt, r0, lds);
-    return;
+  if constexpr (V == RV_GENERIC) {
+    if (a.mode == ROW_INNER) {
+      row_inner<L, RT>(a, mt, r0, lds);
+      return;
+    }
   }
 #if DCV_FULL_TILES
   if (r0 + RT <= mt.m) {
@@ -740,22 +743,29 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
     return;
   }
 #endif
-  row_tile_rows<L, V, RT>(a, mt, img, r0, min(RT, mt.m - r0), lds);
+  row_tile_rows<L, V, RT, NT>(a, mt, img, r0, min(RT, mt.m - r0), lds);
 }
 
 // Tile tables are built on the host in dispatch order (XCD-interleaved, see
 // deconv.hip); entries with image -1 are padding.
 // minimum waves per SIMD the row kernels are compiled for: 6 = three
-// workgroups of 512 threads per compute unit (at most 80 registers)
+// workgroups of 512 threads per compute unit (at most 80 registers); the
+// 1024-thread kernels: 4 = one workgroup per compute unit, 128 registers
 #ifndef DCV_ROW_WAVES
 #define DCV_ROW_WAVES 6
 #endif
-template <int L, int V, int RT = rt_for(L)>
-__global__ void __launch_bounds__(kNTR, DCV_ROW_WAVES) row_kernel(RowArgs a) {
+#ifndef DCV_ROW_WAVES_WIDE
+#define DCV_ROW_WAVES_WIDE 4
+#endif
+// NT = kNTR, or kNTRWide for plans with few row tiles (half-height tiles on
+// one image: a shorter dependent chain per tile; not for RV_GENERIC)
+template <int L, int V, int RT = rt_for(L), int NT = kNTR>
+__global__ void __launch_bounds__(NT, NT == kNTR ? DCV_ROW_WAVES : DCV_ROW_WAVES_WIDE) row_kernel(RowArgs a) {
+  static_assert(NT == kNTR || V != RV_GENERIC, "the generic variant runs kNTR threads");
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
   if (t.x < 0 || (a.done && a.done[t.x])) return;
-  row_tile<L, V, RT>(a, t.x, t.y, lds);
+  row_tile<L, V, RT, NT>(a, t.x, t.y, lds);
 }
 
 // one launch for tiles of every line length: dispatch on the tile's length

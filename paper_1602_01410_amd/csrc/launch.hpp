@@ -52,13 +52,28 @@ size_t row_lds_bytes(int L, int rt = 0);
 size_t col_lds_bytes(int L);
 // rt: rows per tile of the group (0 or rt_for(L): the default; rt_half(L) for
 // the lengths of DCV_FOR_EACH_HALF_RT_LEN)
+// wide: kNTRWide threads per half-height tile (plans with few tiles), for
+// every variant but RV_GENERIC
 hipError_t launch_row(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr);
+                      hipEvent_t e1 = nullptr, bool wide = false);
 // one row-pass variant (RV_*): instantiated in its own translation unit
 template <int V>
 hipError_t launch_row_variant(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
-                              hipEvent_t e1) {
+                              hipEvent_t e1, bool wide) {
   void* args[] = {&a};
+  if constexpr (V != RV_GENERIC) {
+    if (wide && rt > 0 && rt != rt_for(L)) {
+      switch (L) {
+#define DCV_CASE(n)                                                                                        \
+  case n: return rt == rt_half(n) ? launch_lds(row_kernel<n, V, rt_half(n), kNTRWide>, grid, lds, s, args, \
+                                               kNTRWide, e0, e1)                                           \
+                                  : hipErrorInvalidValue;
+        DCV_FOR_EACH_HALF_RT_LEN(DCV_CASE)
+#undef DCV_CASE
+      }
+      return hipErrorInvalidValue;
+    }
+  }
   if (L < 0 && -L <= kShortLenMax)
     return launch_lds(row_kernel_multi<V, DCV_SHORT_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
   if (L <= 0) return launch_lds(row_kernel_multi<V, DCV_LEN_ARGS>, grid, lds, s, args, kNTR, e0, e1);
@@ -80,13 +95,13 @@ hipError_t launch_row_variant(int L, int rt, int grid, size_t lds, hipStream_t s
   return hipErrorInvalidValue;
 }
 extern template hipError_t launch_row_variant<RV_PLAIN>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                        hipEvent_t);
+                                                        hipEvent_t, bool);
 extern template hipError_t launch_row_variant<RV_STOREV>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                         hipEvent_t);
+                                                         hipEvent_t, bool);
 extern template hipError_t launch_row_variant<RV_CHECK>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                        hipEvent_t);
+                                                        hipEvent_t, bool);
 extern template hipError_t launch_row_variant<RV_GENERIC>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                          hipEvent_t);
+                                                          hipEvent_t, bool);
 // wide: kNTCWide threads per column tile where the length has that
 // instantiation (has_wide_col), for plans with few tiles
 #define DCV_FOR_EACH_WIDE_COL_LEN(X) X(512) X(576) X(768) X(1024) X(1152) X(1536) X(2048)

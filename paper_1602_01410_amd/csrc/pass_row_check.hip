@@ -5,8 +5,8 @@
 namespace dcv {
 
 template hipError_t launch_row_variant<RV_STOREV>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                  hipEvent_t);
+                                                  hipEvent_t, bool);
 template hipError_t launch_row_variant<RV_CHECK>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                 hipEvent_t);
+                                                 hipEvent_t, bool);
 
 }  // namespace dcv

@@ -4,6 +4,6 @@
 namespace dcv {
 
 template hipError_t launch_row_variant<RV_PLAIN>(int, int, int, size_t, hipStream_t, RowArgs, hipEvent_t,
-                                                 hipEvent_t);
+                                                 hipEvent_t, bool);
 
 }  // namespace dcv
