@@ -758,7 +758,8 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int img, int r0, floa
 #define DCV_ROW_WAVES_WIDE 4
 #endif
 // NT = kNTR, or kNTRWide for plans with few row tiles (half-height tiles on
-// one image: a shorter dependent chain per tile; not for RV_GENERIC)
+// one image: a shorter dependent chain per tile; plain and before-check
+// iterations only)
 template <int L, int V, int RT = rt_for(L), int NT = kNTR>
 __global__ void __launch_bounds__(NT, NT == kNTR ? DCV_ROW_WAVES : DCV_ROW_WAVES_WIDE) row_kernel(RowArgs a) {
   static_assert(NT == kNTR || V != RV_GENERIC, "the generic variant runs kNTR threads");

@@ -53,7 +53,7 @@ size_t col_lds_bytes(int L);
 // rt: rows per tile of the group (0 or rt_for(L): the default; rt_half(L) for
 // the lengths of DCV_FOR_EACH_HALF_RT_LEN)
 // wide: kNTRWide threads per half-height tile (plans with few tiles), for
-// every variant but RV_GENERIC
+// the RV_PLAIN and RV_STOREV variants
 hipError_t launch_row(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr, bool wide = false);
 // one row-pass variant (RV_*): instantiated in its own translation unit
@@ -61,7 +61,9 @@ template <int V>
 hipError_t launch_row_variant(int L, int rt, int grid, size_t lds, hipStream_t s, RowArgs a, hipEvent_t e0,
                               hipEvent_t e1, bool wide) {
   void* args[] = {&a};
-  if constexpr (V != RV_GENERIC) {
+  // the check variant holds more registers: at 1024 threads one workgroup per
+  // compute unit would fit, so it keeps kNTR
+  if constexpr (V == RV_PLAIN || V == RV_STOREV) {
     if (wide && rt > 0 && rt != rt_for(L)) {
       switch (L) {
 #define DCV_CASE(n)                                                                                        \
