@@ -75,10 +75,11 @@ def _small(M, N, K, kind=synth.MASK_BOUNDARY, seed=0, decim=3, missing=0.3, blur
 
 
 @pytest.mark.parametrize("shape", [(512, 512, synth.MASK_EXPLICIT), (256, 2048, synth.MASK_DECIMATE),
-                                   (1024, 1024, synth.MASK_BOUNDARY)])
+                                   (1024, 1024, synth.MASK_BOUNDARY), (18, 512, synth.MASK_BOUNDARY)])
 def test_half_height_row_tiles(torch_cuda, shape):
     """Plans of one width with few row tiles use tiles of half the rows (a
-    512^2 image: 4-row tiles, 256 x 2048: 1-row tiles, 1024^2: 2-row tiles);
+    512^2 image: 4-row tiles, 256 x 2048: 1-row tiles, 1024^2: 2-row tiles,
+    18 x 512: 4-row tiles with a ragged last one), 1024 threads each;
     results agree with the oracle, with the check/store iterations, graphs
     and one BGS-pass variant exercising every row-pass mode."""
     M, N, kind = shape
