@@ -89,14 +89,20 @@ __host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
   return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLds * L;
 }
 // Lengths that also have row tiles of half the rows (rt_for(L) / 2), for
-// plans with too few tiles to fill the chip
-#define DCV_FOR_EACH_HALF_RT_LEN(X) X(512) X(1024) X(2048)
+// plans with too few tiles to fill the chip: those of at least 64 whose
+// default tile height is even (a half tile then lies inside one row block of
+// the spectrum layout)
+#define DCV_FOR_EACH_HALF_RT_LEN(X) \
+  X(64) X(72) X(96) X(128) X(144) X(256) X(288) X(384) X(512) X(1024) X(1536) X(2048)
 #ifndef DCV_RT_SPLIT
 #define DCV_RT_SPLIT 2
 #endif
 __host__ __device__ constexpr int rt_half(int L) {
   return rt_for(L) / DCV_RT_SPLIT > 0 ? rt_for(L) / DCV_RT_SPLIT : 1;
 }
+#define DCV_CASE(n) static_assert(rt_for(n) % rt_half(n) == 0, "half tiles must divide the row blocks");
+DCV_FOR_EACH_HALF_RT_LEN(DCV_CASE)
+#undef DCV_CASE
 __host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLds * L; }
 
 // the twiddle table a workgroup uses for length L (caller synchronises)
