@@ -281,7 +281,7 @@ def main():
     inputs = to_device(problems)
     popts = plan_options(args.workload)
     plan = binding.Plan(descs(problems), batched=1, use_graph=1, check_every=args.check_every, **popts)
-    log("launch shapes (row, column; 1 = per length, 2 = one launch): %s" % (plan.schedule(),))
+    log("launch shapes (row, column; 1 = per length, 2 = one launch, 3 = hybrid): %s" % (plan.schedule(),))
     log("timing %d steps (+%d warmup), %d images, %d px, %d iterations" % (args.steps, args.warmup,
                                                                           len(problems), npx, iters))
     grad = args.workload == "grad_512"

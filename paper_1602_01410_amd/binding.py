@@ -214,7 +214,8 @@ class Plan:
         return yt, v, d
 
     def schedule(self):
-        """(row, column) launch shapes: 1 = per line length, 2 = one launch."""
+        """(row, column) launch shapes: 1 = per line length, 2 = one launch,
+        3 = hybrid (short lengths share one launch)."""
         out = (ctypes.c_int32 * 2)()
         _check(lib().deconv_plan_schedule(self.handle, out), "schedule")
         return tuple(out)
