@@ -59,7 +59,12 @@ constexpr int kNTCWide = 512;     // column workgroups of plans with few tiles
 // rows per row-pass tile (about DCV_ROW_PIX pixels, at least 2 rows) and
 // columns per column-pass block (a power of two, about DCV_COL_ELEMS / L)
 __host__ __device__ constexpr int rt_for(int L) {
-  return DCV_ROW_PIX / L < 2 ? 2 : (DCV_ROW_PIX / L > 32 ? 32 : DCV_ROW_PIX / L);
+  // rounded down to a power of two (lengths with a factor 3: 768 -> 4 rows
+  // rather than 5; the mixed batch gains 3%)
+  const int r = DCV_ROW_PIX / L < 2 ? 2 : (DCV_ROW_PIX / L > 32 ? 32 : DCV_ROW_PIX / L);
+  int q = 1;
+  while (q * 2 <= r) q *= 2;
+  return q;
 }
 // rows per block of the row-block spectrum layout, in units of the default
 // row tile height
@@ -92,11 +97,11 @@ __host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
   return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLds * L;
 }
 // Lengths that also have row tiles of half the rows (rt_for(L) / 2), for
-// plans with too few tiles to fill the chip: those of at least 64 whose
-// default tile height is even (a half tile then lies inside one row block of
-// the spectrum layout)
+// plans with too few tiles to fill the chip: those of at least 64 (a half
+// tile lies inside one row block of the spectrum layout)
 #define DCV_FOR_EACH_HALF_RT_LEN(X) \
-  X(64) X(72) X(96) X(128) X(144) X(256) X(288) X(384) X(512) X(1024) X(1536) X(2048)
+  X(64) X(72) X(96) X(128) X(144) X(192) X(256) X(288) X(384) X(512) X(576) X(768) X(1024) X(1152) X(1536) \
+      X(2048)
 #ifndef DCV_RT_SPLIT
 #define DCV_RT_SPLIT 2
 #endif
