@@ -23,6 +23,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 
+# The paper's own timings (Sec. III-B, Tables I-IV): MATLAB on an Intel Core
+# i7 3.2 GHz with 32 GB, FP64, 256^2 domain, one BGS pass per iteration; a
+# least-squares line through the twelve Proposed-1 rows gives about 8.48 ms
+# per iteration after a fixed start-up cost.
+PAPER_CONTEXT = {"mpx_it_s": 7.7, "ms_per_iter_256x256": 8.48, "workload": "256^2, Proposed-1, Tables I-IV",
+                 "hardware": "Intel Core i7 3.2 GHz, 32 GB, MATLAB (FP64)"}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -125,6 +132,15 @@ def alg_bytes(problems, unobs):
     return row, col
 
 
+def method_bytes_per_iter(problems, unobs):
+    """Algorithmic bytes of one iteration of the method itself (what it must
+    read and write, independent of how the transforms are organised):
+    A = 44 + 4 d/N per pixel: read ytilde 4, v 8, d 8, the blur spectrum 8
+    (complex64); write v 8, d 8, z 4 on the unobserved pixels."""
+    npx = sum(p["M"] * p["N"] for p in problems)
+    return (44.0 + 4.0 * unobs) * npx
+
+
 def read_traffic(name):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources."""
@@ -165,6 +181,41 @@ def copy_bandwidth(mib=1024, reps=5):
     return 2 * n * 4 / best / 1e9
 
 
+def pass_roofline(problems, inputs, iters, check_every, unobs, name):
+    """Per-launch GPU time of each pass (HIP events attached to the
+    dispatches, on the plan's stream) and the modelled bytes per launch: the
+    roofline object of the heavier pass, the other pass as a sub-object."""
+    from paper_1602_01410_amd import binding
+    pplan = binding.Plan(descs(problems), batched=1, use_graph=0, check_every=check_every, profile=1)
+    y, mask, h, lam, mu = inputs
+    pplan.run(y, mask, h, lam, mu, min(iters, 50))
+    pplan.kernel_times()
+    pplan.run(y, mask, h, lam, mu, iters)
+    row_ms, row_n, col_ms, col_n = pplan.kernel_times()
+    pplan.close()
+    rb, cb = alg_bytes(problems, unobs)
+    row_avg, col_avg = row_ms / max(row_n, 1), col_ms / max(col_n, 1)
+    log("row pass %.2f us x %d, column pass %.2f us x %d" % (row_avg * 1e3, row_n, col_avg * 1e3, col_n))
+    if row_ms >= col_ms:
+        kern, avg, ab = "row_kernel", row_avg, rb
+    else:
+        kern, avg, ab = "col_kernel", col_avg, cb
+    achieved = ab / (avg * 1e-3) / 1e9
+    traffic, tk = read_traffic(name)
+    traffic = traffic if (traffic is not None and tk == kern) else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            # measured bytes (counter traffic) over the same launch time
+            "traffic_frac": round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+            "kernel": kern, "launch_us": round(avg * 1e3, 2), "alg_bytes_per_launch": int(ab),
+            "other_pass": {"kernel": "col_kernel" if kern == "row_kernel" else "row_kernel",
+                           "launch_us": round((col_avg if kern == "row_kernel" else row_avg) * 1e3, 2),
+                           "alg_bytes_per_launch": int(cb if kern == "row_kernel" else rb),
+                           "achieved": round((cb / (col_avg * 1e-3) if kern == "row_kernel"
+                                              else rb / (row_avg * 1e-3)) / 1e9, 1)}}
+
+
 def time_runs(plan, inputs, iters, steps, warmup, backward=False):
     """Seconds for `steps` runs (each: setup, init, all iterations; with
     backward also the reverse pass for a fixed dL/dx), and the wall time."""
@@ -185,15 +236,44 @@ def time_runs(plan, inputs, iters, steps, warmup, backward=False):
         step()
     torch.cuda.synchronize()
     s = plan.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record(s)
-    for _ in range(steps):
+    ev[0].record(s)
+    for k in range(steps):
         step()
-    e1.record(s)
+        ev[k + 1].record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall
+    per_step = [ev[k].elapsed_time(ev[k + 1]) / 1e3 for k in range(steps)]
+    time_runs.per_step = per_step
+    return ev[0].elapsed_time(ev[steps]) / 1e3, wall
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baselines(problems, opts=None):
+    """The oracle on every host thread it is given (~12 s of work) and on
+    one thread (~8 s), with the CPU model."""
+    import oracle
+    nthreads = oracle.num_threads()
+    allc = cpu_baseline(problems, target_s=12.0, opts=opts)
+    oracle.set_threads(1)
+    try:
+        one = cpu_baseline(problems, target_s=8.0, opts=opts)
+    finally:
+        oracle.set_threads(nthreads)
+    allc["value"] = round(allc["value"], 4)
+    allc["cpu_model"] = cpu_model()
+    allc["single_thread"] = {"value": round(one["value"], 4), "cores": 1, "sample": one["sample"]}
+    return allc
 
 
 def cpu_baseline(problems, target_s=15.0, opts=None):
@@ -247,6 +327,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-compare", action="store_true")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the 16 x 1024^2 figure of the default line")
     ap.add_argument("--no-kernel-times", action="store_true")
     ap.add_argument("--iters", type=int, default=0, help="override the workload's iteration count")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -286,6 +367,7 @@ def main():
                                                                           len(problems), npx, iters))
     grad = args.workload == "grad_512"
     t, wall = time_runs(plan, inputs, iters, args.steps, args.warmup, backward=grad)
+    per_step = list(time_runs.per_step)
     value = npx * iters * args.steps / t / 1e6
     ms_step = t / args.steps * 1e3
     log("value %.1f Mpx*it/s, %.3f ms/step (wall %.3f s)" % (value, ms_step, wall))
@@ -299,36 +381,15 @@ def main():
     roof = None
     # the byte model below is that of one pass per iteration (plain method)
     if not args.no_kernel_times and not popts:
-        # per-launch GPU time of each pass, HIP events on the plan's stream
-        pplan = binding.Plan(descs(problems), batched=1, use_graph=0, check_every=args.check_every, profile=1)
-        y, mask, h, lam, mu = inputs
-        pplan.run(y, mask, h, lam, mu, min(iters, 50))
-        pplan.kernel_times()
-        pplan.run(y, mask, h, lam, mu, iters)
-        row_ms, row_n, col_ms, col_n = pplan.kernel_times()
+        roof = pass_roofline(problems, inputs, iters, args.check_every, unobs, args.workload)
+        roof["copy_gbs"] = round(copy_bandwidth(), 1)
+        a_iter = method_bytes_per_iter(problems, unobs)
         rb, cb = alg_bytes(problems, unobs)
-        row_avg, col_avg = row_ms / max(row_n, 1), col_ms / max(col_n, 1)
-        log("row pass %.2f us x %d, column pass %.2f us x %d" % (row_avg * 1e3, row_n, col_avg * 1e3, col_n))
-        if row_ms >= col_ms:
-            kern, avg, ab = "row_kernel", row_avg, rb
-        else:
-            kern, avg, ab = "col_kernel", col_avg, cb
-        achieved = ab / (avg * 1e-3) / 1e9
-        traffic, tk = read_traffic(args.workload)
-        traffic = traffic if (traffic is not None and tk == kern) else None
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
-                # measured bytes (counter traffic) over the same launch time
-                "traffic_frac": round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
-                # a plain device copy on this GPU: the practical streaming ceiling
-                "copy_gbs": round(copy_bandwidth(), 1),
-                "kernel": kern, "launch_us": round(avg * 1e3, 2), "alg_bytes_per_launch": int(ab),
-                "other_pass": {"kernel": "col_kernel" if kern == "row_kernel" else "row_kernel",
-                               "launch_us": round((col_avg if kern == "row_kernel" else row_avg) * 1e3, 2),
-                               "achieved": round((cb / (col_avg * 1e-3) if kern == "row_kernel"
-                                                  else rb / (row_avg * 1e-3)) / 1e9, 1)}}
-        pplan.close()
+        # the method's own bytes (A per pixel-iteration) over the timed steps
+        roof["frac_A"] = round(a_iter * iters * args.steps / t / 1e9 / HBM_PEAK_GBS, 4)
+        roof["method_bytes_per_iter"] = int(a_iter)
+        # both passes' modelled bytes over the whole iteration (timed steps)
+        roof["frac_iter"] = round((rb + cb) * iters * args.steps / t / 1e9 / HBM_PEAK_GBS, 4)
 
     if args.workload == "large_1024" and not args.no_batch_compare:
         log("batched vs plain on the 256-image mixed batch")
@@ -340,20 +401,40 @@ def main():
                          ("plain", dict(batched=0, use_graph=0)),
                          ("plain_graph", dict(batched=0, use_graph=1))):
             pl = binding.Plan(descs(bp), check_every=args.check_every, **kw)
-            tt, _ = time_runs(pl, binp, bit, 1, 1)
-            res[mode] = bnpx * bit / tt / 1e6
+            tt, _ = time_runs(pl, binp, bit, 3, 1)
+            res[mode] = bnpx * bit * 3 / tt / 1e6
             log("  %s: %.1f Mpx*it/s (launch shapes %s)" % (mode, res[mode], pl.schedule()))
             pl.close()
             torch.cuda.empty_cache()
         extra["batch_256"] = {"mpx_it_s": {k: round(v, 1) for k, v in res.items()},
-                              "batched_over_plain": round(res["batched_graph"] / res["plain"], 2)}
+                              "batched_over_plain": round(res["batched_graph"] / res["plain"], 2),
+                              "steps_per_mode": 3}
         del binp
+        torch.cuda.empty_cache()
+
+    if args.workload == "large_1024" and not args.no_uniform:
+        # 16 images of the same recipe: a working set (about 0.8 GB) far beyond
+        # the last-level cache, so this figure is HBM-bound, not cache-bound
+        log("16 x 1024^2 (working set beyond the last-level cache)")
+        up, uit, _ = workload("uniform_16x1024")
+        unpx = sum(p["M"] * p["N"] for p in up)
+        uunobs = unobserved_fraction(up)
+        uinp = to_device(up)
+        pl = binding.Plan(descs(up), batched=1, use_graph=1, check_every=args.check_every)
+        tt, _ = time_runs(pl, uinp, uit, 3, 1)
+        pl.close()
+        ur = pass_roofline(up, uinp, uit, args.check_every, uunobs, "uniform_16x1024")
+        ur["frac_A"] = round(method_bytes_per_iter(up, uunobs) * uit * 3 / tt / 1e9 / HBM_PEAK_GBS, 4)
+        extra["uniform_16x1024"] = {"mpx_it_s": round(unpx * uit * 3 / tt / 1e6, 1),
+                                    "ms_per_step": round(tt / 3 * 1e3, 3), "iters": uit, "roofline": ur}
+        log("  %.1f Mpx*it/s" % extra["uniform_16x1024"]["mpx_it_s"])
+        del uinp
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
-        cpu = cpu_baseline(problems, opts=popts)
-        cpu["value"] = round(cpu["value"], 4)
+        cpu = cpu_baselines(problems, opts=popts)
         log("  %s" % cpu)
 
     out = {"metric": "Mpixel*ADMM-iters/s", "value": round(value, 2), "unit": "Mpixel*ADMM-iters/s",
@@ -363,7 +444,10 @@ def main():
            "config": {"workload": args.workload, "description": wdesc, "images": len(problems), "pixels": npx,
                       "iters": iters, "check_every": args.check_every, "unobserved_fraction": round(unobs, 4),
                       "options": popts},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu,
+           "median_ms_per_step": round(1e3 * sorted(per_step)[len(per_step) // 2], 4),
+           # the paper's own timings, for context (another machine, FP64)
+           "paper_context": PAPER_CONTEXT}
     out.update(extra)
     print(json.dumps(out), flush=True)
 

@@ -189,7 +189,11 @@ deconv_status deconv_admm_run(deconv_plan p, const float* y, const uint8_t* mask
 /* `iters` more iterations from the plan's current state (lambda / mu are read
    again).  Outputs as deconv_admm_run.  Plans with explicit masks reuse the mask
    pointer of the last deconv_admm_run, which must still be valid
-   (DECONV_ERR_STATE if there was no run). */
+   (DECONV_ERR_STATE if there was no run).  With opt.adapt_t > 0 the penalty
+   goes on from the last adapted value, for which d is scaled (eq.
+   (varying_penalty)): `mu` is then ignored, except after deconv_state_import,
+   where it starts the adaptation.  So run(a) followed by continue(b) equals
+   run(a + b). */
 deconv_status deconv_admm_continue(deconv_plan p, const float* lambda, const float* mu,
                                    int32_t iters, float* x_out, float* ytilde_out,
                                    deconv_stats* stats);
@@ -214,16 +218,30 @@ deconv_status deconv_state_import(deconv_plan p, const uint8_t* mask, const floa
  *   grad_y       packed float, dL/dy, zero at unobserved pixels
  *   grad_lambda  float [batch]
  *   grad_h       packed float [ksize_b^2 per image]
- * Recomputes the forward iterations between checkpoints.
+ *   run_id       the id deconv_plan_run_id gave right after that run: if the
+ *                plan has run, continued or imported a state since, the
+ *                checkpoints are another run's and the call returns
+ *                DECONV_ERR_STATE; 0 skips the check
+ * Recomputes the forward iterations between checkpoints.  The reverse pass
+ * uses the forward state (ytilde, v, d) as scratch: afterwards
+ * deconv_admm_continue and deconv_state_export return DECONV_ERR_STATE until
+ * the next run.  The checkpoints stay, so the same reverse pass can be asked
+ * for again.  DECONV_ERR_NO_CHECKPOINTS without a checkpointed run.
  */
 deconv_status deconv_admm_backward(deconv_plan p, const float* y, const uint8_t* mask,
                                    const float* h, const float* lambda, const float* mu,
                                    const float* grad_x, float* grad_y, float* grad_lambda,
-                                   float* grad_h);
+                                   float* grad_h, uint64_t run_id);
+
+/* Id of the state the plan holds (host call): a new, process-unique value
+   after every deconv_admm_run, deconv_admm_continue and deconv_state_import;
+   0 when the plan holds no state (before a run, after a reverse pass). */
+deconv_status deconv_plan_run_id(deconv_plan p, uint64_t* out);
 
 /* Blur spectrum H^ = DFT2(h embedded circularly centred at the origin) for
    every image (device float2 packed, full height x width per image); built with
-   the library's own FFT.  Synchronous. */
+   the library's own FFT.  Synchronous.  The plan's own blur spectrum, state and
+   checkpoints are left as they were. */
 deconv_status deconv_blur_spectrum(deconv_plan p, const float* h, float* spectrum_out);
 
 /* Batched 2-D complex DFT with the library's FFT (unnormalised; inverse = 1

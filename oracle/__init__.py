@@ -14,22 +14,28 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "_oracle.so")
+# ORACLE_LIB names another build of oracle.c to load instead (the sanitizer
+# test runs the pins against an ASan/UBSan build)
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "_oracle.so")
 _lib = None
 
 PHI = {"tv": 0, "quad": 1}
 
 
-def build(force=True):
-    """Compile oracle.c into _oracle.so (gcc, -O3, OpenMP, IEEE semantics)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-           _SRC, "-o", tmp, "-lm"]
+def build(force=True, out=None, sanitize=False):
+    """Compile oracle.c into _oracle.so (gcc, -O3, OpenMP, IEEE semantics);
+    sanitize=True: an AddressSanitizer + UndefinedBehaviorSanitizer build
+    (-O1 -g) into `out`."""
+    out = out or _LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined"] if sanitize else ["-O3"]
+    cmd = ["gcc"] + opt + ["-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, out)
+    return out
 
 
 def lib():
@@ -69,6 +75,7 @@ def _declare(L):
     L.or_objective.restype = ctypes.c_double
     L.or_admm_backward.argtypes = [_I, _I, _I, _D, _D, _U8, _F, _F, _F, _I, _I, _D, _D, _D, _D]
     L.or_num_threads.restype = ctypes.c_int
+    L.or_set_threads.argtypes = [_I]
 
 
 def _d(a):
@@ -83,6 +90,11 @@ def _u8(a):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().or_set_threads(int(n))
 
 
 def fft1(x, sign=-1):

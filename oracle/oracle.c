@@ -26,7 +26,29 @@
  *   around the central m x n region; the oracle takes the mask as given so
  *   that the fully observed special cases can be exercised too.
  *
- * Parity status of each function is stated where it is defined.
+ * Parity pins (tests/test_oracle_pins.py, tests/test_oracle_color.py): each
+ * exported function is checked against something other than itself.
+ *   or_fft1, or_fft2, or_dft2_direct  numpy.fft, each other, Parseval
+ *   or_psf_spectrum       the kappa(H) values printed in Table I and the
+ *                         appendix tables (256^2 domain, sigma = sqrt(l))
+ *   or_conv_direct, or_conv_fft  scipy.signal.convolve2d on the valid part,
+ *                         each other, the adjoint identity
+ *   or_grad, or_gradT     numpy.roll differences, the adjoint identity, the
+ *                         4 sin^2 spectrum of the stencil
+ *   or_init_state         numpy.pad(mode='edge') of the central region (holes
+ *                         at numpy's mean of the observed pixels), numpy.roll
+ *                         differences for v^0
+ *   or_admm_iterate       closed forms (lambda = 0; quadratic phi: Tikhonov
+ *                         and dense normal equations), a dense standard ADMM,
+ *                         Lemmas 2 and 3, the x-step normal equations; passes:
+ *                         the dense joint (x, z) minimiser; penalty update:
+ *                         the decisions of eq. (varying_penalty) on built
+ *                         states and the invariance of mu d
+ *   or_admm_iterate_vec   reduces to or_admm_iterate (C = 1, lambda = 0,
+ *                         equal channels)
+ *   or_warm_start         the dense minimiser of f + tau/2 |x|^2
+ *   or_objective          decreases to the dense minimum
+ *   or_admm_backward      central finite differences of or_admm_iterate
  */
 #include <complex.h>
 #include <math.h>
@@ -909,5 +931,16 @@ int or_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* threads of the parallel loops that follow (timing only; the arithmetic
+   does not depend on it) */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

@@ -20,9 +20,10 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported size", 3: "singular bl
 
 
 class DeconvError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, stats=None):
         super().__init__("%s: %s (status %d)" % (where, STATUS.get(code, "?"), code))
         self.code = code
+        self.stats = stats   # per-image statistics, when the call filled them
 
 
 class ImageDesc(ctypes.Structure):
@@ -50,8 +51,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_create",
            "deconv_plan_destroy", "deconv_admm_run", "deconv_admm_continue", "deconv_state_export",
-           "deconv_state_import", "deconv_admm_backward", "deconv_blur_spectrum", "deconv_fft2",
-           "deconv_plan_kernel_times", "deconv_plan_schedule", "deconv_status_str")
+           "deconv_state_import", "deconv_admm_backward", "deconv_plan_run_id", "deconv_blur_spectrum",
+           "deconv_fft2", "deconv_plan_kernel_times", "deconv_plan_schedule", "deconv_status_str")
 
 _lib = None
 
@@ -75,7 +76,8 @@ def lib():
         L.deconv_admm_continue.argtypes = [P, P, P, I32, P, P, ctypes.POINTER(Stats)]
         L.deconv_state_export.argtypes = [P, P, P, P]
         L.deconv_state_import.argtypes = [P, P, P, P, P, P]
-        L.deconv_admm_backward.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        L.deconv_admm_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.c_uint64]
+        L.deconv_plan_run_id.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
         L.deconv_blur_spectrum.argtypes = [P, P, P]
         L.deconv_fft2.argtypes = [I32, I32, I32, P, I32, P]
         L.deconv_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
@@ -89,9 +91,9 @@ def lib():
     return _lib
 
 
-def _check(code, where):
+def _check(code, where, stats=None):
     if code != 0:
-        raise DeconvError(code, where)
+        raise DeconvError(code, where, stats)
 
 
 def _ptr(t):
@@ -141,7 +143,7 @@ class Plan:
     deconv_options.  The plan allocates its own workspace on the current
     device and runs on `stream` (torch stream, default: current)."""
 
-    def __init__(self, images, stream=None, **opts):
+    def __init__(self, images, stream=None, workspace=None, **opts):
         self.images = [dict(d) for d in images]
         self.opts = default_options(**opts)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -149,9 +151,13 @@ class Plan:
         self.ksq = [int(d["ksize"]) ** 2 for d in images]
         self.npx = sum(self.sizes)
         self.handle = ctypes.c_void_p()
+        # workspace: a caller-owned device tensor of at least workspace_size
+        # bytes (kept alive by the plan), or None for a plan-owned one
+        self.workspace = workspace
+        wp, wn = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
         descs = _descs(images)
         _check(lib().deconv_plan_create(ctypes.byref(self.handle), len(images), descs, ctypes.byref(self.opts),
-                                        _stream_ptr(self.stream), None, 0), "plan_create")
+                                        _stream_ptr(self.stream), wp, wn), "plan_create")
 
     @property
     def batch(self):
@@ -182,24 +188,37 @@ class Plan:
         dev = y.device
         x_out = x_out if x_out is not None else torch.empty(self.npx, dtype=torch.float32, device=dev)
         st = self._stats(stats)
-        _check(lib().deconv_admm_run(self.handle, _ptr(y), _ptr(mask), _ptr(h), _ptr(lam), _ptr(mu),
-                                     int(iters), _ptr(x_out), _ptr(ytilde_out), st), "admm_run")
+        code = lib().deconv_admm_run(self.handle, _ptr(y), _ptr(mask), _ptr(h), _ptr(lam), _ptr(mu),
+                                     int(iters), _ptr(x_out), _ptr(ytilde_out), st)
+        # non-finite values (status 4) are reported per image in the stats
+        _check(code, "admm_run", self._stats_list(st) if code == 4 else None)
         return x_out, self._stats_list(st)
 
     def cont(self, lam, mu, iters, x_out, ytilde_out=None, stats=False):
         st = self._stats(stats)
-        _check(lib().deconv_admm_continue(self.handle, _ptr(lam), _ptr(mu), int(iters), _ptr(x_out),
-                                          _ptr(ytilde_out), st), "admm_continue")
+        code = lib().deconv_admm_continue(self.handle, _ptr(lam), _ptr(mu), int(iters), _ptr(x_out),
+                                          _ptr(ytilde_out), st)
+        _check(code, "admm_continue", self._stats_list(st) if code == 4 else None)
         return x_out, self._stats_list(st)
 
-    def backward(self, y, mask, h, lam, mu, grad_x):
+    def backward(self, y, mask, h, lam, mu, grad_x, run_id=0):
+        """Reverse pass through the last run; run_id (from run_id() right
+        after that run, 0 = unchecked) makes it fail with status 8 when the
+        plan has run since."""
         dev = y.device
         gy = torch.empty(self.npx, dtype=torch.float32, device=dev)
         gl = torch.empty(self.batch, dtype=torch.float32, device=dev)
         gh = torch.empty(sum(self.ksq), dtype=torch.float32, device=dev)
         _check(lib().deconv_admm_backward(self.handle, _ptr(y), _ptr(mask), _ptr(h), _ptr(lam), _ptr(mu),
-                                          _ptr(grad_x), _ptr(gy), _ptr(gl), _ptr(gh)), "admm_backward")
+                                          _ptr(grad_x), _ptr(gy), _ptr(gl), _ptr(gh), ctypes.c_uint64(run_id)),
+               "admm_backward")
         return gy, gl, gh
+
+    def run_id(self):
+        """Id of the state the plan holds (0: none)."""
+        out = ctypes.c_uint64(0)
+        _check(lib().deconv_plan_run_id(self.handle, ctypes.byref(out)), "run_id")
+        return out.value
 
     def blur_spectrum(self, h):
         out = torch.empty(2 * self.npx, dtype=torch.float32, device=h.device)
@@ -265,6 +284,9 @@ class DeconvADMM(torch.autograd.Function):
     def forward(ctx, y, h, lam, plan, mask, mu, iters):
         x, _ = plan.run(y, mask, h, lam, mu, iters)
         ctx.plan = plan
+        # the reverse pass replays this run's checkpoints: if the plan runs
+        # again before backward(), the library refuses (status 8)
+        ctx.run_id = plan.run_id()
         ctx.save_for_backward(y, h, lam, mu)
         ctx.mask = mask
         return x
@@ -272,7 +294,7 @@ class DeconvADMM(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx):
         y, h, lam, mu = ctx.saved_tensors
-        gy, gl, gh = ctx.plan.backward(y, ctx.mask, h, lam, mu, gx.contiguous())
+        gy, gl, gh = ctx.plan.backward(y, ctx.mask, h, lam, mu, gx.contiguous(), run_id=ctx.run_id)
         return gy, gh, gl, None, None, None, None
 
 

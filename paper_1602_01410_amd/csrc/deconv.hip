@@ -17,6 +17,7 @@
 #include <new>
 #include <vector>
 #include <cstdint>
+#include <atomic>
 
 #include "../../include/deconv.h"
 #include "launch.hpp"
@@ -253,6 +254,9 @@ struct deconv_plan_s {
   bool wide_row = false;     // half-height row tiles of kNTRWide threads (few tiles)
   int last_iters = 0;   // iterations of the last run (for the backward)
   bool ck_valid = false;
+  bool mu_valid = false;   // mu_cur holds an adapted penalty (adapt_t > 0)
+  uint64_t run_id = 0;     // id of the state the plan holds (0: none)
+  uint64_t ck_run_id = 0;  // id of the run whose checkpoints the plan holds
 
   // per-launch timing (opt.profile): event pairs around row / column passes
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_row, ev_col;
@@ -746,7 +750,14 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
 // ---------------------------------------------------------------------------
 // run
 // ---------------------------------------------------------------------------
-static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out) {
+// ids of the states plans hold: unique in the process, never 0
+static std::atomic<uint64_t> g_run_id{0};
+static uint64_t new_run_id() { return ++g_run_id; }
+
+// H^ of every image into the grid in specB (free between calls: the column
+// pass output is rebuilt by every prologue); pack = also store the half
+// spectrum the passes read (deconv_blur_spectrum leaves it alone)
+static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out, bool pack = true) {
   hipStream_t s = p->stream;
   float2* grid = reinterpret_cast<float2*>(p->specB);
   const int B = p->batch;
@@ -764,8 +775,10 @@ static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* ful
                             hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(p->hsum + b, g, sizeof(float2), hipMemcpyDeviceToDevice, s));
   }
-  hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
-  HIPCHK(hipGetLastError());
+  if (pack) {
+    hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
+    HIPCHK(hipGetLastError());
+  }
   std::vector<float2> hs(B);
   HIPCHK(hipMemcpyAsync(hs.data(), p->hsum, sizeof(float2) * B, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -993,6 +1006,12 @@ static deconv_status autotune(deconv_plan_s* p) {
   p->col_sched = cs;
   p->row_groups = p->row_sets[rs];
   p->col_groups = p->col_sets[cs];
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_run_id(deconv_plan p, uint64_t* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  *out = p->have_state ? p->run_id : 0;
   return DECONV_OK;
 }
 
@@ -1275,6 +1294,7 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   hipStream_t s = p->stream;
   p->have_state = false;
   p->ck_valid = false;
+  p->run_id = 0;
   p->mask = mask;
   STCHK(setup_spectrum(p, h, nullptr));
   STCHK(reset_counters(p));
@@ -1285,14 +1305,18 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   hipLaunchKernelGGL(init_state_kernel, dim3(256, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean,
                      kMeanBlocks, p->yt, p->v, p->dbuf[0]);
   HIPCHK(hipGetLastError());
-  if (p->opt.adapt_t > 0)
+  if (p->opt.adapt_t > 0) {
     HIPCHK(hipMemcpyAsync(p->mu_cur, mu, sizeof(float) * p->batch, hipMemcpyDeviceToDevice, s));
+    p->mu_valid = true;
+  }
   STCHK(prologue_from_state(p, mu_in_use(p, mu)));
   if (p->opt.warm_iters > 0) STCHK(warm_start(p, mask, lambda, mu));
   STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
   p->have_state = true;
   p->last_iters = iters;
   p->ck_valid = ckpt;
+  p->run_id = new_run_id();
+  p->ck_run_id = ckpt ? p->run_id : 0;
   return finish(p, iters, ytilde_out, stats, mu_in_use(p, mu));
 }
 
@@ -1302,9 +1326,14 @@ extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda
   if (!p->have_state) return DECONV_ERR_STATE;
   if (needs_mask(p) && !p->mask) return DECONV_ERR_STATE;
   p->ck_valid = false;
+  p->run_id = new_run_id();
   STCHK(reset_counters(p));
-  if (p->opt.adapt_t > 0)
+  // the adaptive penalty goes on from the last adapted mu, for which d is
+  // scaled; only a state without one (imported) starts from the caller's
+  if (p->opt.adapt_t > 0 && !p->mu_valid) {
     HIPCHK(hipMemcpyAsync(p->mu_cur, mu, sizeof(float) * p->batch, hipMemcpyDeviceToDevice, p->stream));
+    p->mu_valid = true;
+  }
   STCHK(prologue_from_state(p, mu_in_use(p, mu)));
   STCHK(iterate(p, p->mask, lambda, mu, iters, x_out, false));
   return finish(p, iters, ytilde_out, stats, mu_in_use(p, mu));
@@ -1335,12 +1364,14 @@ extern "C" deconv_status deconv_state_import(deconv_plan p, const uint8_t* mask,
   HIPCHK(hipMemcpyAsync(p->dbuf[0], d, sizeof(float2) * n, hipMemcpyDeviceToDevice, s));
   p->have_state = true;
   p->ck_valid = false;
+  p->mu_valid = false;
+  p->run_id = new_run_id();
   return DECONV_OK;
 }
 
 extern "C" deconv_status deconv_blur_spectrum(deconv_plan p, const float* h, float* spectrum_out) {
   if (!p || !h || !spectrum_out) return DECONV_ERR_INVALID_ARG;
-  deconv_status st = setup_spectrum(p, h, spectrum_out);
+  deconv_status st = setup_spectrum(p, h, spectrum_out, false);
   if (st != DECONV_OK) return st;
   HIPCHK(hipStreamSynchronize(p->stream));
   return DECONV_OK;

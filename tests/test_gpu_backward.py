@@ -96,3 +96,44 @@ def test_backward_few_tiles_matches_batch():
     (y1, l1, h1), (y8, l8, h8) = out
     log("grad_y %.2e grad_h %.2e grad_lambda %.2e" % (rel_l2(y8, y1), rel_l2(h8, h1), abs(l8 - l1) / abs(l1)))
     assert rel_l2(y8, y1) <= 1e-6 and rel_l2(h8, h1) <= 1e-6 and abs(l8 - l1) <= 1e-6 * abs(l1)
+
+
+def test_backward_names_its_run():
+    """The reverse pass replays the checkpoints of the run it names: after a
+    second forward on the plan, the autograd function of the first refuses
+    (status 8) instead of returning the second run's gradient; a blur
+    spectrum query in between changes nothing; the same reverse pass asked
+    for twice gives the same gradients."""
+    import torch
+    from paper_1602_01410_amd import binding
+    probs = _problems()
+    plan = binding.Plan([desc(p) for p in probs], ckpt_every=3, max_iters=9)
+    y, mask, h, lam, mu = device_inputs(probs)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    gx = torch.randn(y.numel(), generator=g).cuda()
+    x1, _ = plan.run(y, mask, h, lam, mu, 9)
+    rid = plan.run_id()
+    assert rid != 0
+    gy1, gl1, gh1 = plan.backward(y, mask, h, lam, mu, gx, run_id=rid)
+    gy2, gl2, gh2 = plan.backward(y, mask, h, lam, mu, gx, run_id=rid)
+    assert plan.run_id() == 0      # the forward state was used as scratch
+    plan.blur_spectrum(h * 0.5)
+    gy3, gl3, gh3 = plan.backward(y, mask, h, lam, mu, gx, run_id=rid)
+    torch.cuda.synchronize()
+    for a, b in ((gy1, gy2), (gl1, gl2), (gh1, gh2), (gy1, gy3), (gl1, gl3), (gh1, gh3)):
+        assert torch.equal(a, b)
+    plan.run(y * 1.1, mask, h, lam, mu, 9)
+    assert plan.run_id() not in (0, rid)
+    with pytest.raises(binding.DeconvError) as e:
+        plan.backward(y, mask, h, lam, mu, gx, run_id=rid)
+    assert e.value.code == 8
+    # the autograd function: two forwards on one plan, then the first's backward
+    yy = y.clone().requires_grad_(True)
+    xa = binding.admm(yy, h, lam, plan, mask, mu, 9)
+    xb = binding.admm(yy, h, lam, plan, mask, mu, 9)
+    with pytest.raises(binding.DeconvError) as e:
+        (xa * gx).sum().backward()
+    assert e.value.code == 8
+    (xb * gx).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.isfinite(yy.grad).all()

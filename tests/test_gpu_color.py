@@ -89,3 +89,23 @@ def test_demosaic_workload_full_size(alpha):
     r = _oracle_colour(p, p["iters"], passes=p["passes"], adapt_t=p["adapt_t"], alpha=alpha)
     log("mu GPU %.4g oracle %.4g" % (st[0]["mu"], r["mu"]))
     _check(p, xs, yts, st, r, 0, "demosaic", yt_rel=5e-4 if alpha == 2.0 else 1e-4)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.xfail(reason="at the paper's lambda = 1e-5 the adapted mu falls to about 3e-5, where the zeros of "
+                          "the 8x8 box's spectrum leave the x-step too ill-conditioned for FP32 to follow the "
+                          "FP64 iterates to 1e-4; the gap is logged", strict=False)
+def test_demosaic_at_the_papers_lambda():
+    """The demosaicing workload with the paper's lambda = 1e-5 (Sec. III-C)
+    instead of the 1e-4 the workload uses: logs the FP32-vs-FP64 gap of x,
+    ytilde and the adapted mu, then holds x to the 1e-4 bar."""
+    from .gpu_util import rel_l2
+    p = synth.rgb_problem(288, 256, 9, seed=synth.BASE_SEED + 5, bsnr=40.0, lam=1e-5, mu=1e-3)
+    iters, passes, t = 200, 4, 3.0
+    xs, yts, st = _gpu_colour([p], iters, bgs_passes=passes, adapt_t=t, check_every=10, use_graph=1)
+    r = _oracle_colour(p, iters, passes=passes, adapt_t=t)
+    log("paper's lambda 1e-5: mu GPU %.4g oracle %.4g" % (st[0]["mu"], r["mu"]))
+    for c in range(3):
+        log("  ch%d x rel_l2 %.3e  ytilde rel_l2 %.3e" % (c, rel_l2(xs[c], r["x"][c]), rel_l2(yts[c], r["yt"][c])))
+    for c in range(3):
+        assert_parity(xs[c], r["x"][c], what="lambda 1e-5 ch%d x" % c)

@@ -2,10 +2,11 @@
 times (batched, graph replay, residual check every 10 iterations).
 
 * 1024^2 / 500 iterations: the whole image against the FP64 oracle.
-* 2048^2 inpainting: the oracle at full size for 40 iterations, and, at the
-  full 300 iterations, the one-iteration relations of the method checked on
-  the HIP path's own state (they hold at any size).
-* the 256-image mixed batch: sampled images against the oracle.
+* 2048^2 inpainting: the whole image against the oracle at the full 300
+  iterations (and at 40); at 300 also the one-iteration relations of the
+  method checked on the HIP path's own state.
+* the 256-image mixed batch: one boundary and one decimated image of every
+  side (128 ... 1024) against the oracle.
 * early stopping on the residual test.
 """
 import numpy as np
@@ -27,6 +28,20 @@ def test_large_1024_full_500_iterations():
     log("1024^2 x 500 it: GPU")
     g = gpu_run([p], p["iters"], **BENCH_OPTS)
     log("1024^2 x 500 it: oracle (FP64, %d threads)" % oracle.num_threads())
+    r = oracle_run(p, p["iters"])
+    assert_parity(g["x"][0], r["x"], what="x")
+    assert_parity(g["yt"][0], r["yt"], what="ytilde")
+
+
+@pytest.mark.timeout(500)
+def test_inpaint_2048_full_300_iterations():
+    """The inpainting workload (2048^2, 21x21 motion blur, boundaries + 50%
+    missing pixels) at its full 300 iterations, whole image against the FP64
+    oracle."""
+    p = synth.config_inpaint_2048()
+    log("2048^2 x %d it: GPU" % p["iters"])
+    g = gpu_run([p], p["iters"], **BENCH_OPTS)
+    log("2048^2 x %d it: oracle (FP64, %d threads)" % (p["iters"], oracle.num_threads()))
     r = oracle_run(p, p["iters"])
     assert_parity(g["x"][0], r["x"], what="x")
     assert_parity(g["yt"][0], r["yt"], what="ytilde")
@@ -106,18 +121,22 @@ def test_inpaint_2048_full_300_iterations_step_relations():
     assert r_x <= 1e-4 and r_z <= 1e-5 and obs_same and r_v <= 1e-5 and r_d <= 1e-5
 
 
-@pytest.mark.timeout(400)
+@pytest.mark.timeout(600)
 def test_mixed_batch_256_sampled_images():
-    """The 256-image batch as bench.py runs it; the images of the three
-    smallest sizes that occur first are compared with the oracle."""
+    """The 256-image batch as bench.py runs it (hybrid launches, graph
+    replay); for every side that occurs, the first boundary-only and the
+    first x4-decimated image are compared with the oracle."""
     probs = synth.config_batch()
     iters = 200
     g = gpu_run(probs, iters, **BENCH_OPTS)
     seen = {}
     for b, p in enumerate(probs):
-        if p["M"] not in seen:
-            seen[p["M"]] = b
-    picks = [seen[s] for s in sorted(seen)[:3]]
+        key = (p["M"], p["mask_kind"])
+        if key not in seen:
+            seen[key] = b
+    picks = [seen[k] for k in sorted(seen)]
+    log("%d sampled images: %s" % (len(picks), sorted(seen)))
+    assert {k[0] for k in seen} == {128, 192, 256, 384, 512, 768, 1024}
     for b in picks:
         p = probs[b]
         log("image %d (%d^2, %s)" % (b, p["M"], "x4 decimated" if p["mask_kind"] == synth.MASK_DECIMATE else "boundary"))

@@ -114,3 +114,28 @@ def test_proposed_ad_full_configuration():
         assert g["stats"][b]["mu"] == pytest.approx(r["mu"], rel=1e-6)
         assert_parity(g["x"][b], r["x"], what="img%d x" % b)
         assert_parity(g["yt"][b], r["yt"], what="img%d ytilde" % b)
+
+
+def test_adaptive_penalty_continue_equals_longer_run():
+    """run(a) then continue(b) with the adaptive penalty goes on from the
+    adapted mu and its rescaled d: the result equals the oracle's run of
+    a + b iterations, and the GPU's own run(a + b) bit for bit."""
+    import torch
+    from paper_1602_01410_amd import binding
+    p = _inpaint_96(mu=0.5)
+    a, b = 17, 23
+    r = oracle_variant(p, a + b, adapt_t=3.0)
+    y, mask, h, lam, mu = device_inputs([p])
+    plan = binding.Plan([desc(p)], adapt_t=3.0, check_every=5)
+    x_one, st_one = plan.run(y, mask, h, lam, mu, a + b, stats=True)
+    x_one = x_one.clone()
+    x = torch.empty_like(y)
+    plan.run(y, mask, h, lam, mu, a, x_out=x)
+    # a different mu passed to continue is ignored: the adapted one goes on
+    _, st = plan.cont(lam, mu * 7.0, b, x, stats=True)
+    torch.cuda.synchronize()
+    log("mu: continued %.6g, one run %.6g, oracle %.6g" % (st[0]["mu"], st_one[0]["mu"], r["mu"]))
+    assert st[0]["mu"] == pytest.approx(r["mu"], rel=1e-6)
+    assert st[0]["mu"] == st_one[0]["mu"]
+    assert_parity(x.cpu().numpy().astype(np.float64).reshape(p["M"], p["N"]), r["x"], what="x")
+    assert torch.equal(x, x_one)

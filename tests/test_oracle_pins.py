@@ -244,6 +244,26 @@ def test_init_state_replicates_border():
     assert not st["dh"].any() and not st["dv"].any()
 
 
+def test_init_state_is_edge_padding():
+    """The initial state against library routines (Sec. III-B: the observed
+    image padded by repeating its border pixels).  With only the boundary band
+    unobserved, ytilde^0 = numpy.pad(y_valid, b, mode='edge'); with holes
+    inside, the holes first take numpy's mean of the observed pixels.  v^0 is
+    the periodic forward difference of ytilde^0 (numpy.roll), d^0 = 0."""
+    for (M, N, K, missing, seed) in ((14, 16, 5, 0.0, 5), (20, 18, 7, 0.35, 6), (12, 12, 3, 0.0, 7)):
+        y, mask, h = small_problem(M, N, K, seed=seed, missing=missing)
+        b = K // 2
+        st = oracle.init_state(y, mask, K)
+        core = y[b:M - b, b:N - b].copy()
+        obs = mask[b:M - b, b:N - b].astype(bool)
+        core[~obs] = np.mean(y[mask.astype(bool)])
+        want = np.pad(core, b, mode="edge")
+        assert np.array_equal(st["yt"], want), (M, N, K, missing)
+        assert np.array_equal(st["vh"], np.roll(want, -1, axis=1) - want)
+        assert np.array_equal(st["vv"], np.roll(want, -1, axis=0) - want)
+        assert not st["dh"].any() and not st["dv"].any()
+
+
 # --------------------------------------------------------------------------
 # closed forms of the whole iteration
 # --------------------------------------------------------------------------
@@ -462,6 +482,94 @@ def test_adaptive_mu_and_passes_reach_same_minimiser():
     mus = ad["hist"][:, 4]
     r = np.log2(mus / 0.05)
     assert np.allclose(r, np.round(r))
+
+
+def _one_step(st, h, mask, lam, mu, adapt_t):
+    """One oracle iteration from a copy of `st`; returns (new state, hist row, mu')."""
+    s = {k: v.copy() for k, v in st.items()}
+    x, hist, mu_f, _ = oracle.admm_iterate(s, h, mask, lam, mu, 1, alpha=2.0, adapt_t=adapt_t)
+    return s, hist[0], mu_f
+
+
+def _check_penalty_step(st, h, mask, lam, mu, t=3.0):
+    """eq. (varying_penalty) on one iteration: the x-, z-, v- and d-steps are
+    those of the fixed penalty; then mu doubles when |d'-d| > t|v'-v| and
+    halves when |v'-v| > t|d'-d|, and the scaled dual d is rescaled so that
+    the unscaled multiplier mu*d is unchanged (halved d with doubled mu and
+    the reverse).  Returns the decision (+1 double, -1 halve, 0 keep)."""
+    fixed, hrow, mu_fixed = _one_step(st, h, mask, lam, mu, 0.0)
+    ad, _, mu_new = _one_step(st, h, mask, lam, mu, t)
+    assert mu_fixed == mu
+    nd, nv = hrow[0], hrow[1]
+    # the steps before the penalty update do not depend on it
+    for k in ("yt", "vh", "vv"):
+        assert np.array_equal(ad[k], fixed[k]), k
+    if nd > t * nv:
+        want = 1
+    elif nv > t * nd:
+        want = -1
+    else:
+        want = 0
+    assert mu_new == mu * {1: 2.0, -1: 0.5, 0: 1.0}[want], (nd, nv, mu, mu_new)
+    # the unscaled multiplier is invariant (powers of two: exact)
+    for k in ("dh", "dv"):
+        assert np.array_equal(mu_new * ad[k], mu * fixed[k]), k
+    return want
+
+
+def test_adaptive_penalty_rule_on_built_states():
+    """Hand-built states on either side of the thresholds of eq.
+    (varying_penalty).  (a) lambda so large that the soft threshold zeroes
+    every u and v = 0: then v' - v = 0 while d' - d = D x' != 0, so mu must
+    double and d halve.  (b) lambda = 0 and d = 0: v' = u = D x', d' = 0
+    (so d' - d = 0 while v' - v = D x' - v != 0): mu must halve (d' = 0 is
+    invariant under the rescaling, so (c) repeats it with d != 0 and a tiny
+    lambda: d' is then tau u/|u| per pixel, |d' - d| stays below |v' - v|/t)."""
+    y, mask, h = small_problem(12, 14, 5, seed=31)
+    st = oracle.init_state(y, mask, 5)
+    mu = 0.05
+    # (a)
+    sa = {k: v.copy() for k, v in st.items()}
+    sa["vh"][:] = 0.0
+    sa["vv"][:] = 0.0
+    assert _check_penalty_step(sa, h, mask, 1e6, mu) == 1
+    # the halving of d is visible (d' = u != 0)
+    ad, _, mu_new = _one_step(sa, h, mask, 1e6, mu, 3.0)
+    fx, _, _ = _one_step(sa, h, mask, 1e6, mu, 0.0)
+    assert mu_new == 2 * mu and np.abs(fx["dh"]).max() > 0
+    np.testing.assert_array_equal(ad["dh"], 0.5 * fx["dh"])
+    # (b)
+    sb = {k: v.copy() for k, v in st.items()}
+    sb["vh"][:] = 0.0
+    sb["vv"][:] = 0.0
+    assert _check_penalty_step(sb, h, mask, 0.0, mu) == -1
+    # (c)
+    rng = _rng(32)
+    sc = {k: v.copy() for k, v in st.items()}
+    sc["dh"] = 1e-4 * rng.standard_normal(sc["dh"].shape)
+    sc["dv"] = 1e-4 * rng.standard_normal(sc["dv"].shape)
+    sc["vh"][:] = 0.0
+    sc["vv"][:] = 0.0
+    assert _check_penalty_step(sc, h, mask, 1e-9, mu) == -1
+    ad, _, mu_new = _one_step(sc, h, mask, 1e-9, mu, 3.0)
+    fx, _, _ = _one_step(sc, h, mask, 1e-9, mu, 0.0)
+    assert mu_new == 0.5 * mu and np.abs(fx["dh"]).max() > 0
+    np.testing.assert_array_equal(ad["dh"], 2.0 * fx["dh"])
+
+
+def test_adaptive_penalty_rule_along_a_run():
+    """Every iteration of an adaptive run (t = 3, the value of Sec. III-B)
+    obeys eq. (varying_penalty) and keeps mu*d invariant; the run takes all
+    three decisions."""
+    y, mask, h = small_problem(16, 16, 5, seed=33, missing=0.2)
+    lam = 1e-3
+    st = oracle.init_state(y, mask, 5)
+    mu = 1e-2
+    seen = set()
+    for _ in range(60):
+        seen.add(_check_penalty_step(st, h, mask, lam, mu))
+        x, hist, mu, _ = oracle.admm_iterate(st, h, mask, lam, mu, 1, alpha=2.0, adapt_t=3.0)
+    assert seen == {1, -1, 0}, seen
 
 
 def test_warm_start_fixed_point():
