@@ -264,6 +264,29 @@ deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out);
 
 const char* deconv_status_str(deconv_status s);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * deconv_plan_create + deconv_admm_run + deconv_plan_destroy in one call,
+ * whose workspace is a device array inside the library (64 MiB, one copy per
+ * GPU, held until the process ends) instead of an allocation.  Arguments as
+ * those three calls; the call allocates no device memory and creates no
+ * streams, events or graphs, so opt.use_graph, opt.profile and opt.tune_cache
+ * are ignored and schedule 0 (autotuning) means 3 (hybrid).  opt.ckpt_every
+ * must be 0 (DECONV_ERR_INVALID_ARG): no plan is left for a reverse pass.  A
+ * batch whose workspace (deconv_plan_workspace_size) exceeds 64 MiB returns
+ * DECONV_ERR_OOM (one 1024 x 1024 image fits).  Host-side bookkeeping uses the
+ * C++ heap.  Every call on one GPU uses the same array: calls that overlap on
+ * one GPU (other streams, other threads) race and give undefined results;
+ * calls on one stream are ordered.  The array keeps the last call's contents;
+ * each call clears what it needs cleared.
+ */
+deconv_status deconv_admm_run_static(int32_t batch, const deconv_image_desc* desc,
+                                     const deconv_options* opt, void* stream, const float* y,
+                                     const uint8_t* mask, const float* h, const float* lambda,
+                                     const float* mu, int32_t iters, float* x_out, float* ytilde_out,
+                                     deconv_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
 EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_create",
            "deconv_plan_destroy", "deconv_admm_run", "deconv_admm_continue", "deconv_state_export",
            "deconv_state_import", "deconv_admm_backward", "deconv_plan_run_id", "deconv_blur_spectrum",
-           "deconv_fft2", "deconv_plan_kernel_times", "deconv_plan_schedule", "deconv_status_str")
+           "deconv_fft2", "deconv_plan_kernel_times", "deconv_plan_schedule", "deconv_status_str",
+           "deconv_admm_run_static")
 
 _lib = None
 
@@ -78,6 +79,8 @@ def lib():
         L.deconv_state_import.argtypes = [P, P, P, P, P, P]
         L.deconv_admm_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.c_uint64]
         L.deconv_plan_run_id.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
+        L.deconv_admm_run_static.argtypes = [I32, ctypes.POINTER(ImageDesc), ctypes.POINTER(Options), P, P, P, P,
+                                             P, P, I32, P, P, ctypes.POINTER(Stats)]
         L.deconv_blur_spectrum.argtypes = [P, P, P]
         L.deconv_fft2.argtypes = [I32, I32, I32, P, I32, P]
         L.deconv_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
@@ -262,6 +265,19 @@ class Plan:
             out.append(flat[o:o + n].view(*shape))
             o += n
         return out
+
+
+def run_static(images, y, mask, h, lam, mu, iters, x_out, ytilde_out=None, stats=False, stream=None, **opts):
+    """deconv_admm_run_static: one whole run (plan, setup, iterations) whose
+    workspace is the library's static device array: the call allocates no
+    device memory (x_out and the optional ytilde_out are the caller's)."""
+    o = default_options(**opts)
+    d = _descs(images)
+    st = (Stats * len(images))() if stats else None
+    _check(lib().deconv_admm_run_static(len(images), d, ctypes.byref(o), _stream_ptr(stream), _ptr(y), _ptr(mask),
+                                        _ptr(h), _ptr(lam), _ptr(mu), int(iters), _ptr(x_out), _ptr(ytilde_out), st),
+           "admm_run_static")
+    return x_out, Plan._stats_list(st)
 
 
 def fft2(data, inverse=False, stream=None):
