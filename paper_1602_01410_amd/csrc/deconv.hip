@@ -187,6 +187,12 @@ struct deconv_plan_s {
   hipStream_t stream = nullptr;     // the caller's stream: every call runs here
   hipStream_t cap_stream = nullptr; // private stream, used only to capture graphs
   hipStream_t ls = nullptr;         // stream the launch helpers enqueue on
+  // graph branches: while a graph is captured, the launches of one pass
+  // (one per line length) fork onto these streams and join again, so that
+  // their kernels overlap in the replayed graph
+  std::vector<hipStream_t> side;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
   std::vector<ImgMeta> meta;
 
   void* ws = nullptr;
@@ -614,6 +620,9 @@ extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
   if (!p) return DECONV_ERR_INVALID_ARG;
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (auto st : p->side) (void)hipStreamDestroy(st);
+  for (auto e : p->join_ev) (void)hipEventDestroy(e);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   for (auto& e : p->ev_row) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& e : p->ev_col) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& e : p->ev_pool) (void)hipEventDestroy(e);
@@ -743,6 +752,20 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
     return fail(DECONV_ERR_HIP);
   deconv_status st = autotune(p);
   if (st != DECONV_OK) return fail(st);
+  if (p->opt.use_graph && p->opt.batched) {
+    // one side stream per extra launch of the longer pass (at most 7)
+    const size_t n = std::min<size_t>(7, std::max(p->row_groups.size(), p->col_groups.size()) - 1);
+    for (size_t k = 0; k < n; ++k) {
+      hipStream_t ss = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&ss, hipStreamNonBlocking) != hipSuccess) return fail(DECONV_ERR_HIP);
+      p->side.push_back(ss);
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail(DECONV_ERR_HIP);
+      p->join_ev.push_back(ev);
+    }
+    if (n > 0 && hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess)
+      return fail(DECONV_ERR_HIP);
+  }
   *out = p;
   return DECONV_OK;
 }
@@ -870,15 +893,49 @@ static const std::vector<Group> pass_groups(deconv_plan_s* p, bool rows) {
   return g;
 }
 
+// Streams of the launches of one pass.  While a graph is being captured and
+// the pass has several launches (images of different lengths: independent
+// work), launch k > 0 goes to a side stream that waits for the fork point,
+// and the capture stream joins them all afterwards: the graph then holds the
+// launches as parallel branches.  Otherwise everything goes to p->ls.
+struct PassStreams {
+  deconv_plan_s* p;
+  size_t n;
+  bool fork;
+  PassStreams(deconv_plan_s* p_, size_t n_) : p(p_), n(n_) {
+    fork = n > 1 && !p->side.empty() && p->ls == p->cap_stream && p->cap_stream != nullptr;
+  }
+  hipError_t begin() { return fork ? hipEventRecord(p->fork_ev, p->ls) : hipSuccess; }
+  hipStream_t stream(size_t k) const { return (fork && k > 0) ? p->side[(k - 1) % p->side.size()] : p->ls; }
+  hipError_t before(size_t k) {
+    if (!fork || k == 0 || k > p->side.size()) return hipSuccess;
+    return hipStreamWaitEvent(stream(k), p->fork_ev, 0);
+  }
+  hipError_t end() {
+    if (!fork) return hipSuccess;
+    const size_t m = std::min(n - 1, p->side.size());
+    for (size_t q = 0; q < m; ++q) {
+      hipError_t e = hipEventRecord(p->join_ev[q], p->side[q]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(p->ls, p->join_ev[q], 0);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
 // launch the row pass over every image (batched) or image by image
 static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
   PassTimer timer(p, &p->ev_row);
   const std::vector<Group>& gs = p->opt.batched ? p->row_groups : pass_groups(p, true);
+  PassStreams ps(p, gs.size());
+  HIPCHK(ps.begin());
   for (size_t k = 0; k < gs.size(); ++k) {
     a.tiles = p->d_tiles + gs[k].tile0;
-    HIPCHK(launch_row(gs[k].L, gs[k].rt, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k),
+    HIPCHK(ps.before(k));
+    HIPCHK(launch_row(gs[k].L, gs[k].rt, gs[k].ntiles, gs[k].lds, ps.stream(k), a, timer.start(k),
                       timer.stop(k, gs.size()), p->wide_row));
   }
+  HIPCHK(ps.end());
   timer.done();
   return DECONV_OK;
 }
@@ -886,11 +943,15 @@ static deconv_status launch_rows(deconv_plan_s* p, RowArgs a) {
 static deconv_status launch_cols(deconv_plan_s* p, ColArgs a) {
   PassTimer timer(p, &p->ev_col);
   const std::vector<Group>& gs = p->opt.batched ? p->col_groups : pass_groups(p, false);
+  PassStreams ps(p, gs.size());
+  HIPCHK(ps.begin());
   for (size_t k = 0; k < gs.size(); ++k) {
     a.tiles = p->d_tiles + gs[k].tile0;
-    HIPCHK(launch_col(gs[k].L, gs[k].ntiles, gs[k].lds, p->ls, a, timer.start(k), timer.stop(k, gs.size()),
+    HIPCHK(ps.before(k));
+    HIPCHK(launch_col(gs[k].L, gs[k].ntiles, gs[k].lds, ps.stream(k), a, timer.start(k), timer.stop(k, gs.size()),
                       p->wide_col && has_wide_col(gs[k].L)));
   }
+  HIPCHK(ps.end());
   timer.done();
   return DECONV_OK;
 }
@@ -1162,6 +1223,9 @@ static deconv_status copy_ckpt(deconv_plan_s* p, int slot, bool to_store) {
   return DECONV_OK;
 }
 
+// iterations per replayed graph when residuals are never checked
+constexpr int kGraphChunk = 10;
+
 // iterate from the current spectra; handles checkpoints, graphs, stopping
 static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
                              int iters, float* x_out, bool record_ckpt) {
@@ -1175,10 +1239,12 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
   }
   int it = 0;
   while (it < iters) {
-    // graph replay of whole check periods (no checkpoint inside, not the last)
-    if (p->opt.use_graph && K > 0 && ck == 0 && it % K == 0 && it + K < iters) {
+    // graph replay of whole check periods (no checkpoint inside, not the
+    // last); without checks, of chunks of kGraphChunk iterations
+    const int G = K > 0 ? K : kGraphChunk;
+    if (p->opt.use_graph && ck == 0 && it % G == 0 && it + G < iters) {
       const int cur0 = p->cur_d;
-      std::vector<uintptr_t> key = {(uintptr_t)K, (uintptr_t)cur0, (uintptr_t)mask, (uintptr_t)lam,
+      std::vector<uintptr_t> key = {(uintptr_t)G, (uintptr_t)cur0, (uintptr_t)mask, (uintptr_t)lam,
                                     (uintptr_t)mu, (uintptr_t)x_out};
       auto g = p->graphs.find(key);
       if (g == p->graphs.end()) {
@@ -1189,8 +1255,8 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
         HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         p->ls = p->cap_stream;
         deconv_status st = DECONV_OK;
-        for (int q = 0; q < K && st == DECONV_OK; ++q)
-          st = launch_iteration(p, mask, lam, mu, flags_for(p, q, iters + K), x_out, nullptr, nullptr, K);
+        for (int q = 0; q < G && st == DECONV_OK; ++q)
+          st = launch_iteration(p, mask, lam, mu, flags_for(p, q, iters + G), x_out, nullptr, nullptr, K);
         hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
         p->ls = p->stream;
         p->cur_d = cur0;   // capturing ran nothing
@@ -1202,8 +1268,8 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
         g = p->graphs.emplace(key, exec).first;
       }
       HIPCHK(hipGraphLaunch(g->second, s));
-      if ((K * d_swaps_per_iter(p)) % 2) p->cur_d = 1 - cur0;
-      it += K;
+      if ((G * d_swaps_per_iter(p)) % 2) p->cur_d = 1 - cur0;
+      it += G;
       if (stopping) {
         std::vector<int> dn(p->batch);
         HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * p->batch, hipMemcpyDeviceToHost, s));
