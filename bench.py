@@ -132,6 +132,51 @@ def alg_bytes(problems, unobs):
     return row, col
 
 
+def bwd_alg_bytes(problems):
+    """Modelled bytes per launch of the reverse passes (each input and output
+    once; halo re-reads excluded).
+    reverse row pass  per pixel: spectra in and out 32*nh/n' + ub in 8 + u 8
+                      + y-bar or z-bar read 4 and write 4 + ub out 8
+    reverse col pass  per half-spectrum element: spectra in 16 + blur spectrum
+                      8 + stored (Y, X) 16 + FP64 blur-gradient sum read and
+                      written 32 + spectra out 16"""
+    row = col = 0.0
+    for p in problems:
+        M, N = p["M"], p["N"]
+        nh = N // 2 + 1
+        row += M * nh * 32.0 + M * N * 32.0
+        col += M * nh * 88.0
+    return row, col
+
+
+def reverse_roofline(problems, inputs, iters, opts):
+    """Per-launch time and modelled bytes of the reverse row and column
+    passes (HIP events on the plan's stream; the reverse pass runs outside
+    graphs when profiled)."""
+    import torch
+    from paper_1602_01410_amd import binding
+    pplan = binding.Plan(descs(problems), batched=1, use_graph=0, profile=1, **opts)
+    y, mask, h, lam, mu = inputs
+    g = torch.Generator(device="cpu").manual_seed(7)
+    gx = (torch.randn(pplan.npx, generator=g) / pplan.npx).cuda()
+    pplan.run(y, mask, h, lam, mu, iters)
+    pplan.backward(y, mask, h, lam, mu, gx)
+    pplan.kernel_times()
+    pplan.bwd_kernel_times()
+    pplan.run(y, mask, h, lam, mu, iters)
+    pplan.backward(y, mask, h, lam, mu, gx)
+    brow_ms, brow_n, bcol_ms, bcol_n = pplan.bwd_kernel_times()
+    pplan.close()
+    rb, cb = bwd_alg_bytes(problems)
+    ra, ca = brow_ms / max(brow_n, 1), bcol_ms / max(bcol_n, 1)
+    log("reverse row pass %.2f us x %d, reverse column pass %.2f us x %d" % (ra * 1e3, brow_n, ca * 1e3, bcol_n))
+    return {"bound": "hbm", "kernel": "bwd_row_kernel", "launch_us": round(ra * 1e3, 2),
+            "alg_bytes_per_launch": int(rb), "achieved": round(rb / (ra * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(rb / (ra * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "other_pass": {"kernel": "bwd_col_kernel", "launch_us": round(ca * 1e3, 2),
+                           "alg_bytes_per_launch": int(cb), "achieved": round(cb / (ca * 1e-3) / 1e9, 1)}}
+
+
 def method_bytes_per_iter(problems, unobs):
     """Algorithmic bytes of one iteration of the method itself (what it must
     read and write, independent of how the transforms are organised):
@@ -192,7 +237,21 @@ def pass_roofline(problems, inputs, iters, check_every, unobs, name):
     pplan.kernel_times()
     pplan.run(y, mask, h, lam, mu, iters)
     row_ms, row_n, col_ms, col_n = pplan.kernel_times()
+    small = pplan.tiles()[3] == 1
     pplan.close()
+    if small:
+        # whole-image-in-LDS path: one launch per check period reads and
+        # writes the state once (ytilde 4, v 8, d 8 each way per pixel) and
+        # reads the blur half spectrum (8 per entry); x (4) on the last
+        avg = row_ms / max(row_n, 1)
+        ab = sum(40.0 * p["M"] * p["N"] + 8.0 * p["M"] * (p["N"] // 2 + 1) for p in problems)
+        log("whole-image-in-LDS launch %.2f us x %d" % (avg * 1e3, row_n))
+        return {"bound": "hbm", "achieved": round(ab / (avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ab / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None, "traffic_frac": None,
+                "kernel": "small_kernel", "launch_us": round(avg * 1e3, 2), "alg_bytes_per_launch": int(ab),
+                "iters_per_launch": check_every or 50,
+                "note": "the image stays in LDS for a whole check period; LDS traffic and workgroup barriers, "
+                        "not HBM, bound this path"}
     rb, cb = alg_bytes(problems, unobs)
     row_avg, col_avg = row_ms / max(row_n, 1), col_ms / max(col_n, 1)
     log("row pass %.2f us x %d, column pass %.2f us x %d" % (row_avg * 1e3, row_n, col_avg * 1e3, col_n))
@@ -377,6 +436,8 @@ def main():
         extra["forward_only_ms_per_step"] = round(tf / args.steps * 1e3, 4)
         extra["reverse_ms_per_step"] = round((t - tf) / args.steps * 1e3, 4)
         log("forward %.3f ms, reverse %.3f ms per step" % (tf / args.steps * 1e3, (t - tf) / args.steps * 1e3))
+        if not args.no_kernel_times:
+            extra["reverse_roofline"] = reverse_roofline(problems, inputs, iters, popts)
 
     roof = None
     # the byte model below is that of one pass per iteration (plain method)

@@ -132,6 +132,25 @@ typedef struct {
                            the working set stays in the last-level cache),
                            1 = ordinary stores, 2 = non-temporal stores.
                            Results do not depend on it.  Default 0. */
+  int32_t row_tiles;    /* row-pass tile height: 0 = autotuned with the launch
+                           shapes (schedule 0) or chosen by the plan's size,
+                           1 = the default height (about 4096 pixels per
+                           tile), 2 = half of it (plans whose images share
+                           one width and keep no checkpoints; otherwise 1).
+                           Results do not depend on it.  Default 0. */
+  int32_t row_threads;  /* threads per half-height row tile: 0 = as
+                           row_tiles, 512 or 1024.  Default 0. */
+  int32_t col_threads;  /* threads per column tile of length >= 512: 0 = as
+                           row_tiles, 256 or 512.  Default 0. */
+  int32_t small_images; /* 1: plans whose images are all square with a side
+                           of 32, 48, 64, 72 or 96 and that use one BGS pass,
+                           a fixed penalty, grey images and no checkpoints
+                           run every iteration of a check period in one
+                           workgroup per image, the image held in LDS (one
+                           launch per check period instead of two per
+                           iteration); 0: never (default: on MI355X the
+                           two-pass kernels are as fast for one 72^2 image
+                           and faster for batches of small images). */
 } deconv_options;
 
 typedef struct {
@@ -222,7 +241,9 @@ deconv_status deconv_state_import(deconv_plan p, const uint8_t* mask, const floa
  *                plan has run, continued or imported a state since, the
  *                checkpoints are another run's and the call returns
  *                DECONV_ERR_STATE; 0 skips the check
- * Recomputes the forward iterations between checkpoints.  The reverse pass
+ * Recomputes the forward iterations between checkpoints; with opt.use_graph
+ * the whole reverse pass is captured once per argument set as one graph and
+ * replayed on later calls.  The reverse pass
  * uses the forward state (ytilde, v, d) as scratch: afterwards
  * deconv_admm_continue and deconv_state_export return DECONV_ERR_STATE until
  * the next run.  The checkpoints stay, so the same reverse pass can be asked
@@ -254,13 +275,27 @@ deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* d
    the last call, from HIP events on the plan's stream (synchronises).
    out[0] = row-pass milliseconds, out[1] = row-pass launches,
    out[2] = column-pass milliseconds, out[3] = column-pass launches.
-   Passes replayed inside a graph are not bracketed. */
+   Passes replayed inside a graph are not bracketed.  On the
+   whole-image-in-LDS path (deconv_plan_tiles out[3] = 1) out[0..1] count
+   its launches (one per check period) and out[2..3] are 0. */
 deconv_status deconv_plan_kernel_times(deconv_plan p, double* out);
+
+/* As deconv_plan_kernel_times for the passes of the reverse pass
+   (deconv_admm_backward): out[0] = reverse row-pass milliseconds, out[1] =
+   launches, out[2] = reverse column-pass milliseconds, out[3] = launches.
+   With opt.profile = 1 the reverse pass runs outside graphs. */
+deconv_status deconv_plan_bwd_kernel_times(deconv_plan p, double* out);
 
 /* Launch shapes in use (after autotuning): out[0] = row pass, out[1] =
    column pass, each 1 (one launch per line length), 2 (one launch for all
    lengths) or 3 (hybrid, see deconv_options.schedule).  Host call. */
 deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out);
+
+/* Tile knobs in use (after autotuning), host call: out[0] = row tile
+   height class (1 default, 2 half), out[1] = threads per half-height row
+   tile (512 or 1024), out[2] = threads per long column tile (256 or 512),
+   out[3] = 1 if the plan runs the whole-image-in-LDS path (small_images). */
+deconv_status deconv_plan_tiles(deconv_plan p, int32_t* out);
 
 const char* deconv_status_str(deconv_status s);
 

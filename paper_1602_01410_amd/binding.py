@@ -40,7 +40,9 @@ class Options(ctypes.Structure):
                 ("tune_cache", ctypes.c_char_p), ("bgs_passes", ctypes.c_int32),
                 ("adapt_t", ctypes.c_double), ("warm_iters", ctypes.c_int32),
                 ("warm_tau", ctypes.c_float), ("channels", ctypes.c_int32),
-                ("spectra_hint", ctypes.c_int32)]
+                ("spectra_hint", ctypes.c_int32), ("row_tiles", ctypes.c_int32),
+                ("row_threads", ctypes.c_int32), ("col_threads", ctypes.c_int32),
+                ("small_images", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -52,7 +54,9 @@ class Stats(ctypes.Structure):
 EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_create",
            "deconv_plan_destroy", "deconv_admm_run", "deconv_admm_continue", "deconv_state_export",
            "deconv_state_import", "deconv_admm_backward", "deconv_plan_run_id", "deconv_blur_spectrum",
-           "deconv_fft2", "deconv_plan_kernel_times", "deconv_plan_schedule", "deconv_status_str",
+           "deconv_fft2", "deconv_plan_kernel_times", "deconv_plan_bwd_kernel_times", "deconv_plan_schedule",
+           "deconv_plan_tiles",
+           "deconv_status_str",
            "deconv_admm_run_static")
 
 _lib = None
@@ -84,7 +88,9 @@ def lib():
         L.deconv_blur_spectrum.argtypes = [P, P, P]
         L.deconv_fft2.argtypes = [I32, I32, I32, P, I32, P]
         L.deconv_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+        L.deconv_plan_bwd_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
         L.deconv_plan_schedule.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.deconv_plan_tiles.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         L.deconv_status_str.argtypes = [I32]
         L.deconv_status_str.restype = ctypes.c_char_p
         for f in EXPORTS:
@@ -242,11 +248,24 @@ class Plan:
         _check(lib().deconv_plan_schedule(self.handle, out), "schedule")
         return tuple(out)
 
+    def tiles(self):
+        """(row tile class 1/2, threads per half-height row tile, threads per
+        long column tile, 1 if the whole-image-in-LDS path runs) in use."""
+        out = (ctypes.c_int32 * 4)()
+        _check(lib().deconv_plan_tiles(self.handle, out), "tiles")
+        return tuple(out)
+
     def kernel_times(self):
         """(row_ms, row_launches, col_ms, col_launches) since the last call
         (plan created with profile=1; launches outside graphs only)."""
         out = (ctypes.c_double * 4)()
         _check(lib().deconv_plan_kernel_times(self.handle, out), "kernel_times")
+        return tuple(out)
+
+    def bwd_kernel_times(self):
+        """As kernel_times, for the reverse row and column passes."""
+        out = (ctypes.c_double * 4)()
+        _check(lib().deconv_plan_bwd_kernel_times(self.handle, out), "bwd_kernel_times")
         return tuple(out)
 
     def state_import(self, mask, h, yt, v, d):

@@ -21,6 +21,7 @@
 
 #include "../../include/deconv.h"
 #include "launch.hpp"
+#include "small.hpp"
 #include "setup.hpp"
 #include "backward_setup.hpp"
 
@@ -222,6 +223,11 @@ struct deconv_plan_s {
   float2* hsum = nullptr;     // DC term of each spectrum (host check)
   float* mu_cur = nullptr;    // adaptive penalty: current mu per image
   float* dscale = nullptr;    // adaptive penalty: rescale of d per image
+  // whole-image-in-LDS path: image indices grouped by side, one launch per
+  // group (side, first, count)
+  bool small = false;
+  int* d_small = nullptr;
+  std::vector<std::array<int, 3>> small_groups;
   // backward support
   float* ck_yt = nullptr;     // checkpoints: ytilde, v, d per stored iteration
   float2* ck_v = nullptr;
@@ -258,6 +264,8 @@ struct deconv_plan_s {
   bool have_state = false;
   bool wide_col = false;     // column tiles of kNTCWide threads (few tiles)
   bool wide_row = false;     // half-height row tiles of kNTRWide threads (few tiles)
+  // autotuner's choices of the tile knobs (-1: none, the heuristics decide)
+  int tune_half = -1, tune_wrow = -1, tune_wcol = -1;
   int last_iters = 0;   // iterations of the last run (for the backward)
   bool ck_valid = false;
   bool mu_valid = false;   // mu_cur holds an adapted penalty (adapt_t > 0)
@@ -265,12 +273,15 @@ struct deconv_plan_s {
   uint64_t ck_run_id = 0;  // id of the run whose checkpoints the plan holds
 
   // per-launch timing (opt.profile): event pairs around row / column passes
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_row, ev_col;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_row, ev_col, ev_brow, ev_bcol;
   std::vector<hipEvent_t> ev_pool;
 
   // graph cache: one executable graph per (check period, buffer parity,
   // argument pointers); replayed for every whole check period of a run
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  // reverse passes: one graph per argument set and starting d parity, with
+  // the d parity it ends on
+  std::map<std::vector<uintptr_t>, std::pair<hipGraphExec_t, int>> bwd_graphs;
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -278,7 +289,7 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
       off_part, off_done, off_nonf, off_itd, off_stopbuf, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
-      off_dscale;
+      off_dscale, off_small;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
       off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64, off_adj_T;
   size_t total;
@@ -306,6 +317,12 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
       return DECONV_ERR_INVALID_ARG;
     if (opt->channels > 1 && opt->ckpt_every > 0) return DECONV_ERR_INVALID_ARG;
     if (opt->spectra_hint < 0 || opt->spectra_hint > 2) return DECONV_ERR_INVALID_ARG;
+    if (opt->row_tiles < 0 || opt->row_tiles > 2) return DECONV_ERR_INVALID_ARG;
+    if (opt->row_threads != 0 && opt->row_threads != kNTR && opt->row_threads != kNTRWide)
+      return DECONV_ERR_INVALID_ARG;
+    if (opt->col_threads != 0 && opt->col_threads != kNTC && opt->col_threads != kNTCWide)
+      return DECONV_ERR_INVALID_ARG;
+    if (opt->small_images < 0 || opt->small_images > 1) return DECONV_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
       const deconv_image_desc& f = desc[b - b % opt->channels];
       if (desc[b].height != f.height || desc[b].width != f.width || desc[b].ksize != f.ksize)
@@ -353,21 +370,106 @@ static bool has_half_rt(int L) {
 // 16 x 512^2 gains 13%; 2048^2, whose half tiles are single rows with a whole
 // halo line each, loses 9%).  Not with checkpoints: the reverse pass uses the
 // default tiles.
-static bool use_half_rt(const deconv_plan_s* p) {
+static bool half_rt_allowed(const deconv_plan_s* p) {
   std::set<int> ws;
-  long long tiles = 0;
-  for (auto& d : p->desc) {
-    ws.insert(d.width);
-    tiles += (d.height + rt_for(d.width) - 1) / rt_for(d.width);
-  }
-  if (ws.size() != 1 || !has_half_rt(*ws.begin()) || p->opt.ckpt_every != 0) return false;
-  return tiles < (rt_half(*ws.begin()) >= 4 ? 6 : 2) * (long long)num_cus();
+  for (auto& d : p->desc) ws.insert(d.width);
+  return ws.size() == 1 && has_half_rt(*ws.begin()) && p->opt.ckpt_every == 0;
 }
 
-// build per-image metadata and the workspace layout
+static bool half_rt_heuristic(const deconv_plan_s* p) {
+  long long tiles = 0;
+  for (auto& d : p->desc) tiles += (d.height + rt_for(d.width) - 1) / rt_for(d.width);
+  return tiles < (rt_half(p->desc[0].width) >= 4 ? 6 : 2) * (long long)num_cus();
+}
+
+// row tiles of half height: forced by opt.row_tiles, else the autotuner's
+// choice (tune_half), else the heuristic above
+static bool use_half_rt(const deconv_plan_s* p) {
+  if (!half_rt_allowed(p)) return false;
+  if (p->opt.row_tiles > 0) return p->opt.row_tiles == 2;
+  if (p->tune_half >= 0) return p->tune_half != 0;
+  return half_rt_heuristic(p);
+}
+
+static void build_tiles(deconv_plan_s* p, bool half);
+
+// build per-image metadata, tile tables and the workspace layout; the tile
+// and partial tables are sized for either row tile height, so that the
+// autotuner can switch between them without a new workspace
 static void build_layout(deconv_plan_s* p, Layout& lay) {
+  long long ntiles = 0, rt = 0;
+  if (half_rt_allowed(p)) {
+    for (bool h : {false, true}) {
+      build_tiles(p, h);
+      ntiles = std::max(ntiles, (long long)p->h_tiles.size());
+      rt = std::max(rt, p->total_rt);
+    }
+  }
+  build_tiles(p, use_half_rt(p));
+  ntiles = std::max(ntiles, (long long)p->h_tiles.size());
+  rt = std::max(rt, p->total_rt);
   const int B = p->batch;
-  const bool half = use_half_rt(p);
+  const long long px = p->total_px, sp = p->total_sp, hhp = p->total_hh, tab = p->total_tab, tw = p->total_tw;
+
+  const size_t A = 256;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1), A); return r; };
+  lay.off_meta = take(sizeof(ImgMeta) * B);
+  lay.off_tiles = take(sizeof(int4) * ntiles);
+  lay.off_yt = take(sizeof(float) * px);
+  lay.off_d0 = take(sizeof(float2) * px);
+  lay.off_d1 = take(sizeof(float2) * px);
+  lay.off_v = take(sizeof(float2) * px);
+  lay.off_specA = take(sizeof(float4) * sp);
+  lay.off_specB = take(sizeof(float4) * sp);
+  lay.off_hh = take(sizeof(float2) * hhp);
+  lay.off_tab = take(sizeof(float) * tab);
+  lay.off_tw = take(sizeof(float2) * tw);
+  lay.off_part = take(sizeof(double) * 3 * rt);
+  lay.off_done = take(sizeof(int) * B);
+  lay.off_nonf = take(sizeof(int) * B);
+  lay.off_itd = take(sizeof(int) * B);
+  lay.off_stopbuf = take(sizeof(int) * B);
+  lay.off_res = take(sizeof(double) * 3 * B);
+  lay.off_mean = take(sizeof(double) * 2 * kMeanBlocks * B);
+  lay.off_goff = take(sizeof(long long) * B);
+  lay.off_hoff = take(sizeof(long long) * B);
+  lay.off_hsum = take(sizeof(float2) * B);
+  lay.off_mu = take(sizeof(float) * B);
+  lay.off_dscale = take(sizeof(float) * B);
+  lay.off_small = take(sizeof(int) * B);
+  const int ck = p->opt.ckpt_every;
+  if (ck > 0) {
+    const int nck = (p->opt.max_iters + ck - 1) / ck + 1;
+    lay.off_ck_yt = take(sizeof(float) * px * nck);
+    lay.off_ck_v = take(sizeof(float2) * px * nck);
+    lay.off_ck_d = take(sizeof(float2) * px * nck);
+    lay.off_seg_u = take(sizeof(float2) * px * ck);
+    lay.off_seg_spec = take(sizeof(float4) * sp * ck);
+    lay.off_adj_a = take(sizeof(float2) * px);
+    lay.off_adj_b = take(sizeof(float2) * px);
+    lay.off_adj_z = take(sizeof(float) * px);
+    lay.off_adj_y = take(sizeof(float) * px);
+    lay.off_adj_S = take(sizeof(double2) * hhp);
+    lay.off_tw64 = take(sizeof(double2) * tw);
+    lay.off_adj_lam = take(sizeof(double) * rt);
+    lay.off_adj_vb = take(sizeof(float2) * px);
+    lay.off_adj_db = take(sizeof(float2) * px);
+    lay.off_adj_mean = take(sizeof(double) * 64 * B);
+    long long mk = 1;
+    for (auto& d : p->desc) mk = std::max(mk, (long long)d.height * d.ksize);
+    lay.off_adj_T = take(sizeof(double2) * mk * B);
+  } else {
+    lay.off_ck_yt = lay.off_ck_v = lay.off_ck_d = lay.off_seg_u = lay.off_seg_spec = 0;
+    lay.off_adj_a = lay.off_adj_b = lay.off_adj_z = lay.off_adj_y = lay.off_adj_S = lay.off_adj_lam = 0;
+    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = lay.off_tw64 = lay.off_adj_T = 0;
+  }
+  lay.total = o;
+}
+
+// per-image metadata and the tile tables of every launch shape
+static void build_tiles(deconv_plan_s* p, bool half) {
+  const int B = p->batch;
   p->meta.assign(B, ImgMeta{});
   p->hoff_h.assign(B, 0);
   long long px = 0, sp = 0, hhp = 0, tab = 0, rt = 0, hk = 0;
@@ -410,7 +512,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   // Half-height tiles fewer than three per compute unit (one 1024^2 image:
   // 512) run with 1024 threads: a shorter dependent chain per tile (row pass
   // 16.7 -> 15.7 us); batches lose 5-10% that way.
-  p->wide_row = half && rt < 3LL * num_cus();
+  p->wide_row = half && (p->opt.row_threads > 0 ? p->opt.row_threads == kNTRWide
+                                               : p->tune_wrow >= 0 ? p->tune_wrow != 0 : rt < 3LL * num_cus());
   p->total_px = px; p->total_sp = sp; p->total_hh = hhp; p->total_tab = tab; p->total_tw = tw;
   p->total_rt = rt; p->total_h = hk; p->tw_off = twoff;
 
@@ -439,7 +542,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   // workgroups overlap better: 16 x 1024^2, 77 -> 83 us if widened).
   long long ncol = 0;
   for (int b = 0; b < B; ++b) ncol += (long long)ct_tiles[b].size();
-  p->wide_col = ncol < 3LL * num_cus();
+  p->wide_col = p->opt.col_threads > 0 ? p->opt.col_threads == kNTCWide
+                                       : p->tune_wcol >= 0 ? p->tune_wcol != 0 : ncol < 3LL * num_cus();
   size_t rlds = 0, clds = 0;
   const int grt = half ? rt_half(*widths.begin()) : 0;
   for (int w : widths) rlds = std::max(rlds, row_lds_bytes(w, grt));
@@ -520,61 +624,6 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
     one[b] = ct_tiles[b];
     add_group(p->col_img[b], p->meta[b].m, col_lds_bytes(p->meta[b].m), one, 0);
   }
-  const long long ntiles = (long long)p->h_tiles.size();
-
-  const size_t A = 256;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1), A); return r; };
-  lay.off_meta = take(sizeof(ImgMeta) * B);
-  lay.off_tiles = take(sizeof(int4) * ntiles);
-  lay.off_yt = take(sizeof(float) * px);
-  lay.off_d0 = take(sizeof(float2) * px);
-  lay.off_d1 = take(sizeof(float2) * px);
-  lay.off_v = take(sizeof(float2) * px);
-  lay.off_specA = take(sizeof(float4) * sp);
-  lay.off_specB = take(sizeof(float4) * sp);
-  lay.off_hh = take(sizeof(float2) * hhp);
-  lay.off_tab = take(sizeof(float) * tab);
-  lay.off_tw = take(sizeof(float2) * tw);
-  lay.off_part = take(sizeof(double) * 3 * rt);
-  lay.off_done = take(sizeof(int) * B);
-  lay.off_nonf = take(sizeof(int) * B);
-  lay.off_itd = take(sizeof(int) * B);
-  lay.off_stopbuf = take(sizeof(int) * B);
-  lay.off_res = take(sizeof(double) * 3 * B);
-  lay.off_mean = take(sizeof(double) * 2 * kMeanBlocks * B);
-  lay.off_goff = take(sizeof(long long) * B);
-  lay.off_hoff = take(sizeof(long long) * B);
-  lay.off_hsum = take(sizeof(float2) * B);
-  lay.off_mu = take(sizeof(float) * B);
-  lay.off_dscale = take(sizeof(float) * B);
-  const int ck = p->opt.ckpt_every;
-  if (ck > 0) {
-    const int nck = (p->opt.max_iters + ck - 1) / ck + 1;
-    lay.off_ck_yt = take(sizeof(float) * px * nck);
-    lay.off_ck_v = take(sizeof(float2) * px * nck);
-    lay.off_ck_d = take(sizeof(float2) * px * nck);
-    lay.off_seg_u = take(sizeof(float2) * px * ck);
-    lay.off_seg_spec = take(sizeof(float4) * sp * ck);
-    lay.off_adj_a = take(sizeof(float2) * px);
-    lay.off_adj_b = take(sizeof(float2) * px);
-    lay.off_adj_z = take(sizeof(float) * px);
-    lay.off_adj_y = take(sizeof(float) * px);
-    lay.off_adj_S = take(sizeof(double2) * hhp);
-    lay.off_tw64 = take(sizeof(double2) * tw);
-    lay.off_adj_lam = take(sizeof(double) * rt);
-    lay.off_adj_vb = take(sizeof(float2) * px);
-    lay.off_adj_db = take(sizeof(float2) * px);
-    lay.off_adj_mean = take(sizeof(double) * 64 * B);
-    long long mk = 1;
-    for (auto& d : p->desc) mk = std::max(mk, (long long)d.height * d.ksize);
-    lay.off_adj_T = take(sizeof(double2) * mk * B);
-  } else {
-    lay.off_ck_yt = lay.off_ck_v = lay.off_ck_d = lay.off_seg_u = lay.off_seg_spec = 0;
-    lay.off_adj_a = lay.off_adj_b = lay.off_adj_z = lay.off_adj_y = lay.off_adj_S = lay.off_adj_lam = 0;
-    lay.off_adj_vb = lay.off_adj_db = lay.off_adj_mean = lay.off_tw64 = lay.off_adj_T = 0;
-  }
-  lay.total = o;
 }
 
 template <typename T>
@@ -599,6 +648,10 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->warm_tau = 1e-3f;
   opt->channels = 1;
   opt->spectra_hint = 0;
+  opt->row_tiles = 0;
+  opt->row_threads = 0;
+  opt->col_threads = 0;
+  opt->small_images = 0;
   return DECONV_OK;
 }
 
@@ -625,6 +678,9 @@ extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
   if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   for (auto& e : p->ev_row) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& e : p->ev_col) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : p->ev_brow) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : p->ev_bcol) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& kv : p->bwd_graphs) (void)hipGraphExecDestroy(kv.second.first);
   for (auto& e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->own_ws && p->ws) (void)hipFree(p->ws);
   delete p;
@@ -684,6 +740,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   p->hsum = at<float2>(w, lay.off_hsum);
   p->mu_cur = at<float>(w, lay.off_mu);
   p->dscale = at<float>(w, lay.off_dscale);
+  p->d_small = at<int>(w, lay.off_small);
   if (p->opt.ckpt_every > 0) {
     p->ck_yt = at<float>(w, lay.off_ck_yt);
     p->ck_v = at<float2>(w, lay.off_ck_v);
@@ -750,7 +807,26 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
       hipMemsetAsync(p->done, 0, sizeof(int) * batch, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(DECONV_ERR_HIP);
-  deconv_status st = autotune(p);
+  // the whole-image-in-LDS path (asked for with opt.small_images = 1) takes
+  // the plan when every image has one and the options need nothing it lacks
+  // (one pass, fixed penalty, grey images, no checkpoints)
+  p->small = p->opt.small_images == 1 && p->opt.bgs_passes == 1 && !(p->opt.adapt_t > 0) &&
+             p->opt.channels == 1 && p->opt.ckpt_every == 0;
+  for (auto& d : p->desc) p->small = p->small && has_small_path(d.height, d.width);
+  if (p->small) {
+    std::vector<int> order(batch);
+    for (int b = 0; b < batch; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int u, int v) { return p->desc[u].height < p->desc[v].height; });
+    // one launch: of the image's side when all share it, else one that
+    // dispatches on each image's side
+    bool one_side = true;
+    for (auto& d : p->desc) one_side = one_side && d.height == p->desc[0].height;
+    p->small_groups.push_back({one_side ? p->desc[0].height : 0, 0, batch});
+    if (hipMemcpy(p->d_small, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DECONV_ERR_HIP);
+  }
+  deconv_status st = p->small ? DECONV_OK : autotune(p);
   if (st != DECONV_OK) return fail(st);
   if (p->opt.use_graph && p->opt.batched) {
     // one side stream per extra launch of the longer pass (at most 7)
@@ -975,7 +1051,15 @@ static std::string plan_signature(const deconv_plan_s* p) {
   return os.str();
 }
 
-static bool cache_lookup(const char* path, const std::string& key, int* r, int* c) {
+// One line per tuned batch signature: "signature<TAB>rs cs half wrow wcol"
+// (launch shape of each pass, 0-2; row tile height class, wide row tiles and
+// wide column tiles, each 0/1, or -1 for the plan's heuristic).  The last
+// matching line wins; lines of the older two-field form are read too.
+struct TuneChoice {
+  int rs = 1, cs = 1, half = -1, wrow = -1, wcol = -1;
+};
+
+static bool cache_lookup(const char* path, const std::string& key, TuneChoice* out) {
   if (!path) return false;
   std::ifstream f(path);
   std::string line;
@@ -983,96 +1067,167 @@ static bool cache_lookup(const char* path, const std::string& key, int* r, int* 
   while (std::getline(f, line)) {
     const size_t t1 = line.find('\t');
     if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size()) continue;
-    int rr = 0, cc = 0;
-    if (sscanf(line.c_str() + t1 + 1, "%d %d", &rr, &cc) == 2 && rr >= 0 && rr <= 2 && cc >= 0 && cc <= 2) {
-      *r = rr;
-      *c = cc;
-      found = true;   // the last entry wins
+    TuneChoice c;
+    const int n = sscanf(line.c_str() + t1 + 1, "%d %d %d %d %d", &c.rs, &c.cs, &c.half, &c.wrow, &c.wcol);
+    if (n >= 2 && c.rs >= 0 && c.rs <= 2 && c.cs >= 0 && c.cs <= 2) {
+      if (n < 5) c.half = c.wrow = c.wcol = -1;
+      *out = c;
+      found = true;
     }
   }
   return found;
 }
 
-static void cache_store(const char* path, const std::string& key, int r, int c) {
+static void cache_store(const char* path, const std::string& key, const TuneChoice& c) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << "\t" << r << " " << c << "\n";
+  f << key << "\t" << c.rs << " " << c.cs << " " << c.half << " " << c.wrow << " " << c.wcol << "\n";
 }
 
+// rebuild the tile tables for the plan's knob choices and upload them
+static deconv_status apply_tuning(deconv_plan_s* p, const TuneChoice& c) {
+  p->tune_half = c.half;
+  p->tune_wrow = c.wrow;
+  p->tune_wcol = c.wcol;
+  build_tiles(p, use_half_rt(p));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipMemcpy(p->d_meta, p->meta.data(), sizeof(ImgMeta) * p->batch, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->d_tiles, p->h_tiles.data(), sizeof(int4) * p->h_tiles.size(), hipMemcpyHostToDevice));
+  p->row_sched = c.rs;
+  p->col_sched = c.cs;
+  p->row_groups = p->row_sets[c.rs];
+  p->col_groups = p->col_sets[c.cs];
+  return DECONV_OK;
+}
+
+// The autotuner (schedule 0, batched plans): the launch shape of each pass
+// (one launch per line length, one for all, hybrid) and the tile knobs the
+// options leave open -- row tiles of the default or half height, 512 or 1024
+// threads per half-height row tile, 256 or 512 threads per long column tile.
+// Candidates are timed on whole iterations (column pass then row pass, plain
+// iterations on zero data, on the plan's own workspace); the plan's size
+// heuristics give the starting choice, and another wins only when it is at
+// least 3% faster.  Decisions go to the tune cache when one is given.
 static deconv_status autotune(deconv_plan_s* p) {
   if (p->opt.schedule != 0 || !p->opt.batched) return DECONV_OK;
-  const bool rows = p->row_sets[0].size() > 1, cols = p->col_sets[0].size() > 1;
-  if (!rows && !cols) return DECONV_OK;
-  const std::string key = plan_signature(p);
-  int rs = 1, cs = 1;
-  if (!cache_lookup(p->opt.tune_cache, key, &rs, &cs)) {
-    hipStream_t s = p->stream;
-    const size_t n = (size_t)p->total_px;
-    HIPCHK(hipMemsetAsync(p->yt, 0, sizeof(float) * n, s));
-    HIPCHK(hipMemsetAsync(p->v, 0, sizeof(float2) * n, s));
-    HIPCHK(hipMemsetAsync(p->dbuf[0], 0, sizeof(float2) * n, s));
-    HIPCHK(hipMemsetAsync(p->dbuf[1], 0, sizeof(float2) * n, s));
-    // lambda = 0, mu = 1 and an all-unobserved mask: any finite data will do
-    float* par = nullptr;
-    uint8_t* msk = nullptr;
-    HIPCHK(hipMalloc(&par, sizeof(float) * 2 * p->batch));
-    if (hipMalloc(&msk, n) != hipSuccess) { (void)hipFree(par); return DECONV_ERR_OOM; }
-    std::vector<float> hp(2 * p->batch, 0.f);
-    for (int b = 0; b < p->batch; ++b) hp[p->batch + b] = 1.f;
-    deconv_status st = DECONV_OK;
-    double best[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    if (hipMemcpy(par, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemsetAsync(msk, 0, n, s) != hipSuccess) st = DECONV_ERR_HIP;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (st == DECONV_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-      st = DECONV_ERR_HIP;
-    const int kReps = 5;
-    for (int pass = 0; pass < 2 && st == DECONV_OK; ++pass) {
-      for (int k = 0; k < 3 && st == DECONV_OK; ++k) {
-        if (pass == 0) p->row_groups = p->row_sets[k];
-        else p->col_groups = p->col_sets[k];
-        for (int r = 0; r <= kReps && st == DECONV_OK; ++r) {
-          if (r == 1 && hipEventRecord(e0, s) != hipSuccess) st = DECONV_ERR_HIP;
-          if (pass == 0) {
-            RowArgs a = row_args(p, msk, par, par + p->batch);
-            a.mode = ROW_ITER;
-            a.d_in = p->dbuf[0];
-            a.d_out = p->dbuf[1];
-            a.done = nullptr;
-            if (st == DECONV_OK) st = launch_rows(p, a);
-          } else {
-            ColArgs a = col_args(p, par + p->batch);
-            a.done = nullptr;
-            if (st == DECONV_OK) st = launch_cols(p, a);
-          }
-        }
-        float ms = 0.f;
-        if (st == DECONV_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          st = DECONV_ERR_HIP;
-        best[pass][k] = ms;
-      }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(msk);
-    (void)hipFree(par);
-    if (st != DECONV_OK) return st;
-    auto pick = [](const double* t) { return t[0] < t[1] ? (t[0] < t[2] ? 0 : 2) : (t[1] < t[2] ? 1 : 2); };
-    rs = rows ? pick(best[0]) : 1;
-    cs = cols ? pick(best[1]) : 1;
-    cache_store(p->opt.tune_cache, key, rs, cs);
+  const bool multi_r = p->row_sets[0].size() > 1, multi_c = p->col_sets[0].size() > 1;
+  // the heuristics' choice
+  TuneChoice heur;
+  const bool h_half = use_half_rt(p);
+  heur.half = h_half ? 1 : 0;
+  heur.wrow = p->wide_row ? 1 : 0;
+  heur.wcol = p->wide_col ? 1 : 0;
+  std::vector<std::pair<int, int>> rowc = {{heur.half, heur.wrow}};   // (half, wide rows)
+  if (half_rt_allowed(p) && p->opt.row_tiles != 1) {
+    std::vector<int> wr;
+    if (p->opt.row_threads == 0) wr = {0, 1};
+    else wr = {p->opt.row_threads == kNTRWide ? 1 : 0};
+    if (p->opt.row_tiles == 0) rowc.push_back({0, 0});
+    for (int w : wr) rowc.push_back({1, w});
   }
-  p->row_sched = rs;
-  p->col_sched = cs;
-  p->row_groups = p->row_sets[rs];
-  p->col_groups = p->col_sets[cs];
-  return DECONV_OK;
+  std::vector<int> colc = {heur.wcol};
+  bool long_cols = false;
+  for (auto& d : p->desc) long_cols |= has_wide_col(d.height);
+  if (long_cols && p->opt.col_threads == 0) colc = {heur.wcol, 1 - heur.wcol};
+  if (!multi_r && !multi_c && rowc.size() < 2 && colc.size() < 2) return DECONV_OK;
+  const std::string key = plan_signature(p);
+  TuneChoice best = heur;
+  if (cache_lookup(p->opt.tune_cache, key, &best)) return apply_tuning(p, best);
+  hipStream_t s = p->stream;
+  const size_t n = (size_t)p->total_px;
+  HIPCHK(hipMemsetAsync(p->yt, 0, sizeof(float) * n, s));
+  HIPCHK(hipMemsetAsync(p->v, 0, sizeof(float2) * n, s));
+  HIPCHK(hipMemsetAsync(p->dbuf[0], 0, sizeof(float2) * n, s));
+  HIPCHK(hipMemsetAsync(p->dbuf[1], 0, sizeof(float2) * n, s));
+  // lambda = 0, mu = 1 and an all-unobserved mask: any finite data will do
+  float* par = nullptr;
+  uint8_t* msk = nullptr;
+  HIPCHK(hipMalloc(&par, sizeof(float) * 2 * p->batch));
+  if (hipMalloc(&msk, n) != hipSuccess) { (void)hipFree(par); return DECONV_ERR_OOM; }
+  std::vector<float> hp(2 * p->batch, 0.f);
+  for (int b = 0; b < p->batch; ++b) hp[p->batch + b] = 1.f;
+  deconv_status st = DECONV_OK;
+  if (hipMemcpy(par, hp.data(), sizeof(float) * hp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemsetAsync(msk, 0, n, s) != hipSuccess) st = DECONV_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st == DECONV_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    st = DECONV_ERR_HIP;
+  // milliseconds of kReps iterations (after two untimed ones), best of two
+  const int kReps = 10;
+  auto time_iters = [&](double* ms_out) -> deconv_status {
+    double best_ms = 1e300;
+    for (int trial = 0; trial < 2; ++trial) {
+      for (int r = 0; r < kReps + 2; ++r) {
+        if (r == 2 && hipEventRecord(e0, s) != hipSuccess) return DECONV_ERR_HIP;
+        ColArgs ca = col_args(p, par + p->batch);
+        ca.done = nullptr;
+        STCHK(launch_cols(p, ca));
+        RowArgs ra = row_args(p, msk, par, par + p->batch);
+        ra.mode = ROW_ITER;
+        ra.d_in = p->dbuf[r & 1];
+        ra.d_out = p->dbuf[1 - (r & 1)];
+        ra.done = nullptr;
+        STCHK(launch_rows(p, ra));
+      }
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return DECONV_ERR_HIP;
+      best_ms = std::min(best_ms, (double)ms);
+    }
+    *ms_out = best_ms;
+    return DECONV_OK;
+  };
+  // the candidates one at a time, the other pass at its current best;
+  // the first candidate timed is the heuristics' own
+  double best_ms = 1e300;
+  auto consider = [&](const TuneChoice& c) {
+    if (st != DECONV_OK) return;
+    st = apply_tuning(p, c);
+    double ms = 0;
+    if (st == DECONV_OK) st = time_iters(&ms);
+    if (st == DECONV_OK && (best_ms == 1e300 || ms < 0.97 * best_ms)) {
+      best_ms = ms;
+      best = c;
+    }
+  };
+  consider(heur);
+  for (auto& rc : rowc)
+    for (int k = multi_r ? 0 : 1; k <= (multi_r ? 2 : 1); ++k) {
+      TuneChoice c = best;
+      c.half = rc.first;
+      c.wrow = rc.second;
+      c.rs = k;
+      consider(c);
+    }
+  for (int wc : colc)
+    for (int k = multi_c ? 0 : 1; k <= (multi_c ? 2 : 1); ++k) {
+      TuneChoice c = best;
+      c.wcol = wc;
+      c.cs = k;
+      consider(c);
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(msk);
+  (void)hipFree(par);
+  if (st != DECONV_OK) return st;
+  cache_store(p->opt.tune_cache, key, best);
+  return apply_tuning(p, best);
 }
 
 extern "C" deconv_status deconv_plan_run_id(deconv_plan p, uint64_t* out) {
   if (!p || !out) return DECONV_ERR_INVALID_ARG;
   *out = p->have_state ? p->run_id : 0;
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_tiles(deconv_plan p, int32_t* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  out[0] = (!p->meta.empty() && p->meta[0].rt != rt_for(p->meta[0].n)) ? 2 : 1;
+  out[1] = p->wide_row ? kNTRWide : kNTR;
+  out[2] = p->wide_col ? kNTCWide : kNTC;
+  out[3] = p->small ? 1 : 0;
   return DECONV_OK;
 }
 
@@ -1207,7 +1362,7 @@ static deconv_status warm_start(deconv_plan_s* p, const uint8_t* mask, const flo
 
 static deconv_status copy_ckpt(deconv_plan_s* p, int slot, bool to_store) {
   const size_t n = (size_t)p->total_px;
-  hipStream_t s = p->stream;
+  hipStream_t s = p->ls;
   float* yt = p->ck_yt + n * slot;
   float2* v = p->ck_v + n * slot;
   float2* d = p->ck_d + n * slot;
@@ -1303,6 +1458,61 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
   return DECONV_OK;
 }
 
+// Iterations on the whole-image-in-LDS path: one launch per check period (or
+// per kSmallChunk iterations without checks), each followed by the residual
+// kernel when its last iteration is a check.  d stays in its buffer.
+constexpr int kSmallChunk = 50;
+
+static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
+                                   int iters, float* x_out) {
+  hipStream_t s = p->stream;
+  const int K = p->opt.check_every;
+  const bool stopping = K > 0 && (p->opt.tol_primal > 0 || p->opt.tol_dual > 0);
+  int it = 0;
+  while (it < iters) {
+    const int cnt = std::min(K > 0 ? K - it % K : kSmallChunk, iters - it);
+    SmallArgs a{};
+    a.meta = p->d_meta;
+    a.yt = p->yt;
+    a.d = p->dbuf[p->cur_d];
+    a.v = p->v;
+    a.hh = p->hh;
+    a.tab = p->tab;
+    a.mask = mask;
+    a.lam = lam;
+    a.mu = mu;
+    a.tw = p->tw;
+    a.partials = p->partials;
+    a.done = p->done;
+    a.x_out = x_out;
+    a.iters = cnt;
+    a.check = K > 0 && (it + cnt) % K == 0;
+    a.store_x = it + cnt == iters || (a.check && stopping);
+    a.alpha = p->opt.alpha;
+    PassTimer timer(p, &p->ev_row);
+    for (size_t q = 0; q < p->small_groups.size(); ++q) {
+      const auto& g = p->small_groups[q];
+      a.imgs = p->d_small + g[1];
+      HIPCHK(launch_small(g[0], g[0] > 0 ? g[0] : 0, g[2], s, a, timer.start(q), timer.stop(q, p->small_groups.size())));
+    }
+    timer.done();
+    it += cnt;
+    if (a.check) {
+      hipLaunchKernelGGL(residual_kernel, dim3(p->batch), dim3(kNT), 0, s, p->d_meta, p->partials, p->res, p->done,
+                         p->nonfinite, p->iters_done, cnt, 1, p->opt.tol_primal, p->opt.tol_dual, 0.0, p->mu_cur,
+                         p->dscale, p->stop_buf, p->cur_d);
+      HIPCHK(hipGetLastError());
+      if (stopping) {
+        std::vector<int> dn(p->batch);
+        HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * p->batch, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
+      }
+    }
+  }
+  return DECONV_OK;
+}
+
 static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deconv_stats* stats,
                             const float* mu) {
   hipStream_t s = p->stream;
@@ -1377,7 +1587,8 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   }
   STCHK(prologue_from_state(p, mu_in_use(p, mu)));
   if (p->opt.warm_iters > 0) STCHK(warm_start(p, mask, lambda, mu));
-  STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
+  if (p->small) STCHK(iterate_small(p, mask, lambda, mu, iters, x_out));
+  else STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
   p->have_state = true;
   p->last_iters = iters;
   p->ck_valid = ckpt;
@@ -1401,7 +1612,8 @@ extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda
     p->mu_valid = true;
   }
   STCHK(prologue_from_state(p, mu_in_use(p, mu)));
-  STCHK(iterate(p, p->mask, lambda, mu, iters, x_out, false));
+  if (p->small) STCHK(iterate_small(p, p->mask, lambda, mu, iters, x_out));
+  else STCHK(iterate(p, p->mask, lambda, mu, iters, x_out, false));
   return finish(p, iters, ytilde_out, stats, mu_in_use(p, mu));
 }
 
@@ -1461,11 +1673,11 @@ extern "C" deconv_status deconv_fft2(int32_t count, int32_t height, int32_t widt
 
 #include "backward_host.inc"
 
-extern "C" deconv_status deconv_plan_kernel_times(deconv_plan p, double* out) {
-  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+static deconv_status pass_times(deconv_plan_s* p, double* out, bool reverse) {
   HIPCHK(hipStreamSynchronize(p->stream));
   double ms[2] = {0.0, 0.0};
-  std::vector<std::pair<hipEvent_t, hipEvent_t>>* lists[2] = {&p->ev_row, &p->ev_col};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* lists[2] = {reverse ? &p->ev_brow : &p->ev_row,
+                                                              reverse ? &p->ev_bcol : &p->ev_col};
   for (int k = 0; k < 2; ++k) {
     for (auto& e : *lists[k]) {
       float t = 0.f;
@@ -1479,6 +1691,16 @@ extern "C" deconv_status deconv_plan_kernel_times(deconv_plan p, double* out) {
     lists[k]->clear();
   }
   return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_kernel_times(deconv_plan p, double* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  return pass_times(p, out, false);
+}
+
+extern "C" deconv_status deconv_plan_bwd_kernel_times(deconv_plan p, double* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  return pass_times(p, out, true);
 }
 
 extern "C" const char* deconv_status_str(deconv_status s) {

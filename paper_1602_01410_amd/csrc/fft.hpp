@@ -7,7 +7,8 @@
 // = 2^a 3^c.  Each pass of radix R reads R values at stride L/R, applies the
 // twiddles and an R-point DFT in registers, and writes them back in
 // self-sorting (Stockham) order, so no bit reversal is needed.  Passes are
-// radix 16/8/4/2 for the power-of-two part and radix 3 for each factor 3.
+// radix 16/8/4/2 for the power-of-two part, radix 9 for each factor 3^2 and
+// radix 3 for a last factor 3.
 //
 // Conventions: forward = exp(-2 pi i jk/L), inverse = exp(+2 pi i jk/L), both
 // unnormalised (scaling is folded into the spectral solve).
@@ -28,9 +29,9 @@ struct RadixPlan {
   static constexpr int c3 = count3(L);
   static constexpr int a = ilog2(L / pow3(c3));
   static constexpr int np2 = a > 0 ? (a + 3) / 4 : 0;   // radix <= 16 passes
-  static constexpr int npass = np2 + c3;
+  static constexpr int npass = np2 + c3 / 2 + c3 % 2;   // each 3^2 in one radix-9 pass
   static constexpr int radix(int k) {
-    return k < np2 ? (1 << (a / np2 + (k < a % np2 ? 1 : 0))) : 3;
+    return k < np2 ? (1 << (a / np2 + (k < a % np2 ? 1 : 0))) : (k - np2 < c3 / 2 ? 9 : 3);
   }
   static constexpr int ns(int k) { int n = 1; for (int q = 0; q < k; ++q) n *= radix(q); return n; }
   static_assert((1 << a) * pow3(c3) == L, "length must be 2^a 3^c");
@@ -103,6 +104,40 @@ template <bool INV> struct Dft<3, INV> {
   }
 };
 
+// multiply by exp(-+ 2 pi i m / 9) with a constant m (m = 1, 2, 4)
+template <int M, bool INV>
+__device__ __forceinline__ float2 tw9(float2 a) {
+  // cos / sin of 2 pi m / 9
+  constexpr double kc[5] = {1, 0.76604444311897801, 0.17364817766693041, -0.5, -0.93969262078590832};
+  constexpr double ks[5] = {0, 0.64278760968653925, 0.98480775301220802, 0.86602540378443871,
+                            0.34202014332566888};
+  constexpr float c = (float)kc[M];
+  constexpr float s = (float)ks[M];
+  constexpr float sg = INV ? s : -s;   // forward exp(-i theta)
+  return make_float2(a.x * c - a.y * sg, a.x * sg + a.y * c);
+}
+
+// 9 = 3 x 3: inner 3-point DFTs over n1 (stride 3), twiddle W9^(n2 k1), outer
+// 3-point DFTs over n2; output index k1 + 3 k2.
+template <bool INV> struct Dft<9, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 t[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      t[n2][0] = v[n2]; t[n2][1] = v[n2 + 3]; t[n2][2] = v[n2 + 6];
+      Dft<3, INV>::run(t[n2]);
+    }
+    t[1][1] = tw9<1, INV>(t[1][1]); t[1][2] = tw9<2, INV>(t[1][2]);
+    t[2][1] = tw9<2, INV>(t[2][1]); t[2][2] = tw9<4, INV>(t[2][2]);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      float2 u[3] = {t[0][k1], t[1][k1], t[2][k1]};
+      Dft<3, INV>::run(u);
+      v[k1] = u[0]; v[k1 + 3] = u[1]; v[k1 + 6] = u[2];
+    }
+  }
+};
+
 template <bool INV>
 __device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
   float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
@@ -160,6 +195,13 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* 
   w[1] = tw[jm * S];
   if constexpr (R > 2) w[2] = tw[2 * jm * S];
   if constexpr (R == 3) {
+  } else if constexpr (R == 9) {
+    w[3] = cmul(w[1], w[2]);
+    w[4] = tw[4 * jm * S];
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+    w[8] = tw[8 * jm * S];
   } else if constexpr (R >= 4) {
     w[3] = cmul(w[1], w[2]);
     if constexpr (R >= 8) {
@@ -188,8 +230,11 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* 
 // MAXB butterflies.  tw is the LDS table exp(-2 pi i t / L), t < L.
 // The caller must have synchronised after the last write of buf.
 // ---------------------------------------------------------------------------
+// (tid: the thread's index in the workgroup, threadIdx.x unless the caller
+// passes a copy the compiler cannot see through)
 template <int L, int R, int NS, bool INV, int NT, int MAXLINES>
-__device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const float2* tw) {
+__device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const float2* tw,
+                                              unsigned tid = threadIdx.x) {
   constexpr int NB = L / R;
   constexpr int MAXB = (MAXLINES * NB + NT - 1) / NT;
   constexpr int S = L / (NS * R);
@@ -198,7 +243,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
   float2 v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int idx = (int)threadIdx.x + q * NT;
+    const int idx = (int)tid + q * NT;
     if (idx < total) {
       const int line = idx / NB, j = idx - line * NB;
       const float2* src = buf + line * LS;
@@ -213,7 +258,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int idx = (int)threadIdx.x + q * NT;
+    const int idx = (int)tid + q * NT;
     if (idx < total) {
       const int line = idx / NB, j = idx - line * NB;
       const int jm = j % NS;
@@ -232,10 +277,10 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
 }
 
 template <int L, bool INV, int NT, int MAXLINES, int P = 0>
-__device__ __forceinline__ void fft_lines(float2* buf, int nlines, const float2* tw) {
+__device__ __forceinline__ void fft_lines(float2* buf, int nlines, const float2* tw, unsigned tid = threadIdx.x) {
   if constexpr (P < RadixPlan<L>::npass) {
-    stockham_pass<L, RadixPlan<L>::radix(P), RadixPlan<L>::ns(P), INV, NT, MAXLINES>(buf, nlines, tw);
-    fft_lines<L, INV, NT, MAXLINES, P + 1>(buf, nlines, tw);
+    stockham_pass<L, RadixPlan<L>::radix(P), RadixPlan<L>::ns(P), INV, NT, MAXLINES>(buf, nlines, tw, tid);
+    fft_lines<L, INV, NT, MAXLINES, P + 1>(buf, nlines, tw, tid);
   }
 }
 

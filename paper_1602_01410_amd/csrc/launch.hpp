@@ -117,7 +117,14 @@ inline bool has_wide_col(int L) {
 }
 hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr, bool wide = false);
-hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a);
-hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a);
+// whole-image-in-LDS path (small.hpp): square images of a few sides
+struct SmallArgs;
+bool has_small_path(int M, int N);
+hipError_t launch_small(int M, int N, int grid, hipStream_t s, SmallArgs a, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+hipError_t launch_bwd_col(int L, int grid, size_t lds, hipStream_t s, BwdColArgs a, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
 
 }  // namespace dcv

@@ -152,6 +152,12 @@ __global__ void __launch_bounds__(kNT) init_state_kernel(const ImgMeta* meta, co
   }
 }
 
+// n 32-bit words of zeros (instead of a memset node where a graph may be
+// captured)
+__global__ void __launch_bounds__(kNT) zero_words_kernel(unsigned* p, long long n) {
+  for (long long i = (long long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long long)gridDim.x * kNT) p[i] = 0u;
+}
+
 // per image: FP64 sum of the row-tile partials -> |d'-d|, |v'-v|, |z'-z|;
 // with stop_test, sets the stop flag when both tolerances hold; with
 // adapt_t > 0, the penalty update of eq. (varying_penalty): mu doubles (d

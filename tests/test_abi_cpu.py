@@ -59,6 +59,10 @@ def test_host_argument_checks():
            ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, adapt_t=3.0), 1),
            ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, warm_iters=5), 1),
            ([dict(height=64, width=64, ksize=5)], dict(spectra_hint=3), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(row_tiles=3), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(row_threads=256), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(col_threads=1024), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(small_images=2), 1),
            ([], {}, 1)]                                            # empty batch
     for images, opts, code in bad:
         with pytest.raises(binding.DeconvError) as e:

@@ -137,3 +137,29 @@ def test_backward_names_its_run():
     (xb * gx).sum().backward()
     torch.cuda.synchronize()
     assert torch.isfinite(yy.grad).all()
+
+
+def test_reverse_pass_graph_replay():
+    """The reverse pass captured as one graph (use_graph = 1) and replayed
+    gives the gradients of the uncaptured reverse pass bit for bit, also
+    when the contents of grad_x change between replays."""
+    import torch
+    from paper_1602_01410_amd import binding
+    probs = _problems()
+    y, mask, h, lam, mu = device_inputs(probs)
+    g = torch.Generator(device="cpu").manual_seed(11)
+    gx = torch.randn(y.numel(), generator=g).cuda()
+    out = {}
+    for use_graph in (0, 1):
+        plan = binding.Plan([desc(p) for p in probs], ckpt_every=4, max_iters=10, use_graph=use_graph)
+        res = []
+        for rep in range(3):
+            gx.copy_(torch.randn(y.numel(), generator=torch.Generator(device="cpu").manual_seed(20 + rep)).cuda())
+            plan.run(y, mask, h, lam, mu, 10)
+            res.append([t.clone() for t in plan.backward(y, mask, h, lam, mu, gx)])
+        torch.cuda.synchronize()
+        out[use_graph] = res
+    for a, b in zip(out[0], out[1]):
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
+    assert not torch.equal(out[1][0][0], out[1][1][0])
