@@ -99,7 +99,10 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   const int nr = min(RT, M - r0);
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
+  float2* lds_tw = lds + (RT + 1) * LS;
+  const float2* tw_glob = a.tw + mt.twr;
+  TwCopy<L, kNTR, kTwLdsRow> twc;
+  const float2* tw = tw_glob;
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
   const float tau2 = tau * tau;
@@ -121,12 +124,19 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   float sz[KP];
   unsigned obsbits = 0;
   if (!start) {
-    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
+    // the twiddle table's reads travel with the spectra
+    gather_rows<L, RT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb,
+                       [&]() { twc.issue(tw_glob, tid); });
+    tw = twc.commit(lds_tw, tw_glob, tid);
 #if !DCV_BWD_EARLY_STATE
     // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
     __syncthreads();
-    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+    fft_lines<L, true, kNTR, RT + 1, kEarlyTwRow>(buf, nr + 1, tw);
 #endif
+  }
+  if (start) {
+    twc.issue(tw_glob, tid);
+    tw = twc.commit(lds_tw, tw_glob, tid);
   }
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -153,7 +163,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   if (!start) {
     // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
     __syncthreads();
-    fft_lines<L, true, kNTR, RT + 1>(buf, nr + 1, tw);
+    fft_lines<L, true, kNTR, RT + 1, kEarlyTwRow>(buf, nr + 1, tw);
   }
 #endif
 
@@ -257,7 +267,7 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
   constexpr int LS = lstride(L);
   const ImgMeta mt = a.meta[img];
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTC>(lds + 2 * C * LS, a.tw + mt.twc);
+  const float2* tw = twiddle_table<L, kNTC, kTwLdsCol>(lds + 2 * C * LS, a.tw + mt.twc);
   const long long base = mt.sp + (long long)blk * L * C;
   const float4* __restrict__ sin = a.spec_in + base;
   for (int q = threadIdx.x; q < L * C; q += kNTC) {
@@ -267,7 +277,7 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
     buf[(2 * c + 1) * LS + lpad(i)] = make_float2(v.z, v.w);
   }
   __syncthreads();
-  fft_lines<L, false, kNTC, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, false, kNTC, 2 * C, kEarlyTwCol>(buf, 2 * C, tw);
   const float mu = a.mu[img];
   const float mn = (float)L * (float)mt.n;
   const float scale = 1.0f / mn;
@@ -309,7 +319,7 @@ __device__ __forceinline__ void bwd_col_tile(const BwdColArgs& a, int img, int b
     buf[(2 * c + 1) * LS + lpad(ky)] = HR;
   }
   __syncthreads();
-  fft_lines<L, true, kNTC, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, true, kNTC, 2 * C, kEarlyTwCol>(buf, 2 * C, tw);
   float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rb);
   const unsigned nbc = (unsigned)(mt.nb * C);
   for (int q = threadIdx.x; q < L * C; q += kNTC) {

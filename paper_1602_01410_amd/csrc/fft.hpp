@@ -187,31 +187,45 @@ template <bool INV> struct Dft<16, INV> {
 // ---------------------------------------------------------------------------
 // v[k] *= w^k with w = exp(-+2 pi i jm S / L), k = 1..R-1.  The powers w, w^2,
 // w^4, w^8 come from the table (exact up to the float rounding of the table);
-// the others are products of at most three of them.
+// the others are products of at most three of them.  twiddle_base reads the
+// table entries, twiddle_mul forms the other powers and applies them, so that
+// a pass can issue the reads before it waits on the workgroup barrier.
 // ---------------------------------------------------------------------------
-template <int R, int S, bool INV>
-__device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* tw) {
+template <int R>
+struct TwBase {
+  static constexpr int n = R == 2 ? 1 : (R <= 4 ? 2 : (R == 8 ? 3 : 4));
+  float2 w[n];   // w, w^2, w^4, w^8 (as many as radix R needs)
+};
+template <int R, int S>
+__device__ __forceinline__ void twiddle_base(TwBase<R>& b, int jm, const float2* tw) {
+  b.w[0] = tw[jm * S];
+  if constexpr (TwBase<R>::n > 1) b.w[1] = tw[2 * jm * S];
+  if constexpr (TwBase<R>::n > 2) b.w[2] = tw[4 * jm * S];
+  if constexpr (TwBase<R>::n > 3) b.w[3] = tw[8 * jm * S];
+}
+template <int R, bool INV>
+__device__ __forceinline__ void twiddle_mul(float2* v, const TwBase<R>& b) {
   float2 w[R];
-  w[1] = tw[jm * S];
-  if constexpr (R > 2) w[2] = tw[2 * jm * S];
+  w[1] = b.w[0];
+  if constexpr (R > 2) w[2] = b.w[1];
   if constexpr (R == 3) {
   } else if constexpr (R == 9) {
     w[3] = cmul(w[1], w[2]);
-    w[4] = tw[4 * jm * S];
+    w[4] = b.w[2];
     w[5] = cmul(w[4], w[1]);
     w[6] = cmul(w[4], w[2]);
     w[7] = cmul(w[4], w[3]);
-    w[8] = tw[8 * jm * S];
+    w[8] = b.w[3];
   } else if constexpr (R >= 4) {
     w[3] = cmul(w[1], w[2]);
     if constexpr (R >= 8) {
-      w[4] = tw[4 * jm * S];
+      w[4] = b.w[2];
       w[5] = cmul(w[4], w[1]);
       w[6] = cmul(w[4], w[2]);
       w[7] = cmul(w[4], w[3]);
     }
     if constexpr (R >= 16) {
-      w[8] = tw[8 * jm * S];
+      w[8] = b.w[3];
 #pragma unroll
       for (int k = 9; k < 16; ++k) w[k] = cmul(w[8], w[k - 8]);
     }
@@ -223,6 +237,12 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* 
     v[k] = cmul(v[k], t);
   }
 }
+template <int R, int S, bool INV>
+__device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* tw) {
+  TwBase<R> b;
+  twiddle_base<R, S>(b, jm, tw);
+  twiddle_mul<R, INV>(v, b);
+}
 
 // ---------------------------------------------------------------------------
 // one Stockham pass over `nlines` lines of length L stored in LDS
@@ -231,8 +251,10 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* 
 // The caller must have synchronised after the last write of buf.
 // ---------------------------------------------------------------------------
 // (tid: the thread's index in the workgroup, threadIdx.x unless the caller
-// passes a copy the compiler cannot see through)
-template <int L, int R, int NS, bool INV, int NT, int MAXLINES>
+// passes a copy the compiler cannot see through).  With EARLY_TW the twiddle
+// reads are issued together with the data reads, before the barrier, so that
+// a table read from global memory waits on the barrier rather than after it.
+template <int L, int R, int NS, bool INV, int NT, int MAXLINES, bool EARLY_TW = false>
 __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const float2* tw,
                                               unsigned tid = threadIdx.x) {
   constexpr int NB = L / R;
@@ -241,6 +263,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
   constexpr int LS = lstride(L);
   const int total = nlines * NB;
   float2 v[MAXB][R];
+  TwBase<R> wb[EARLY_TW && NS > 1 ? MAXB : 1];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
     const int idx = (int)tid + q * NT;
@@ -253,6 +276,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
         if constexpr (NB % (1 << kPadShift) == 0) v[q][k] = src[lpad(j) + k * lpad(NB)];
         else v[q][k] = src[lpad(j + k * NB)];
       }
+      if constexpr (EARLY_TW && NS > 1) twiddle_base<R, S>(wb[q], j % NS, tw);
     }
   }
   __syncthreads();
@@ -262,7 +286,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
     if (idx < total) {
       const int line = idx / NB, j = idx - line * NB;
       const int jm = j % NS;
-      if constexpr (NS > 1) apply_twiddles<R, S, INV>(v[q], jm, tw);
+      if constexpr (EARLY_TW && NS > 1) twiddle_mul<R, INV>(v[q], wb[q]);
+      else if constexpr (NS > 1) apply_twiddles<R, S, INV>(v[q], jm, tw);
       Dft<R, INV>::run(v[q]);
       float2* dst = buf + line * LS;
       const int base = (j / NS) * NS * R + jm;
@@ -276,11 +301,12 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
   __syncthreads();
 }
 
-template <int L, bool INV, int NT, int MAXLINES, int P = 0>
+template <int L, bool INV, int NT, int MAXLINES, bool EARLY_TW = false, int P = 0>
 __device__ __forceinline__ void fft_lines(float2* buf, int nlines, const float2* tw, unsigned tid = threadIdx.x) {
   if constexpr (P < RadixPlan<L>::npass) {
-    stockham_pass<L, RadixPlan<L>::radix(P), RadixPlan<L>::ns(P), INV, NT, MAXLINES>(buf, nlines, tw, tid);
-    fft_lines<L, INV, NT, MAXLINES, P + 1>(buf, nlines, tw, tid);
+    stockham_pass<L, RadixPlan<L>::radix(P), RadixPlan<L>::ns(P), INV, NT, MAXLINES, EARLY_TW>(buf, nlines, tw,
+                                                                                               tid);
+    fft_lines<L, INV, NT, MAXLINES, EARLY_TW, P + 1>(buf, nlines, tw, tid);
   }
 }
 

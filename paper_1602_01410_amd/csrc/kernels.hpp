@@ -76,25 +76,32 @@ __host__ __device__ constexpr int c_for(int L) {
   while (c * 2 <= DCV_COL_ELEMS / L && c * 2 <= 16) c *= 2;
   return c;
 }
-// Twiddle tables are read from LDS (copied per workgroup) or straight from
-// the global table through the L1 cache.
-#ifndef DCV_TW_GLOBAL
-#define DCV_TW_GLOBAL 1
+// Twiddle tables are read from LDS (copied per workgroup at its start) or
+// straight from the global table through the L1 cache, per pass (bits of
+// DCV_TW_LDS: 1 row passes, 2 column passes).  Measured on MI355X: the LDS
+// copy shortens the row pass (16 x 1024^2: 147 -> 138 us per launch), the
+// global table suits the column pass (its larger LDS footprint would cost a
+// workgroup per compute unit: 76 -> 80 us).
+#ifndef DCV_TW_LDS
+#define DCV_TW_LDS 1
 #endif
-constexpr int kTwLds = DCV_TW_GLOBAL ? 0 : 1;
+constexpr int kTwLdsRow = (DCV_TW_LDS & 1) ? 1 : 0;
+constexpr int kTwLdsCol = (DCV_TW_LDS & 2) ? 1 : 0;
+// Twiddle reads issued before each transform pass's barrier (bits: 1 row
+// passes, 2 column passes); measured to pay for the column pass's global
+// table (mixed 256-image batch: 425 -> 410 us per column launch).
+#ifndef DCV_EARLY_TW
+#define DCV_EARLY_TW 2
+#endif
+constexpr bool kEarlyTwRow = (DCV_EARLY_TW & 1) != 0;
+constexpr bool kEarlyTwCol = (DCV_EARLY_TW & 2) != 0;
 // row pass: full tiles get their own copy of the tile code with the row
 // count as a constant (1) or share the code of the ragged last tiles (0)
 #ifndef DCV_FULL_TILES
 #define DCV_FULL_TILES 0
 #endif
-// row pass: issue the epilogue's state loads before the inverse transform
-// (1) or after it (0: fewer live registers, which lets three 512-thread
-// workgroups share a compute unit; measured faster on MI355X)
-#ifndef DCV_EARLY_STATE
-#define DCV_EARLY_STATE 0
-#endif
 __host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
-  return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLds * L;
+  return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLdsRow * L;
 }
 // Lengths that also have row tiles of half the rows (rt_for(L) / 2), for
 // plans with too few tiles to fill the chip: those of at least 64 (a half
@@ -111,18 +118,48 @@ __host__ __device__ constexpr int rt_half(int L) {
 #define DCV_CASE(n) static_assert(rt_for(n) % rt_half(n) == 0, "half tiles must divide the row blocks");
 DCV_FOR_EACH_HALF_RT_LEN(DCV_CASE)
 #undef DCV_CASE
-__host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLds * L; }
+__host__ __device__ constexpr int col_lds_elems(int L) { return 2 * c_for(L) * lstride(L) + kTwLdsCol * L; }
 
 // the twiddle table a workgroup uses for length L (caller synchronises)
-template <int L, int NT>
+template <int L, int NT, int TW_LDS>
 __device__ __forceinline__ const float2* twiddle_table(float2* lds_tw, const float2* __restrict__ glob) {
-  if constexpr (kTwLds) {
+  if constexpr (TW_LDS) {
     load_twiddles<L, NT>(lds_tw, glob);
     return lds_tw;
   } else {
     return glob;
   }
 }
+
+// The same copy split in two: issue() reads the thread's entries of the
+// global table into registers, commit() writes them to LDS and returns the
+// table to use; the reads can then travel with a tile's other loads.
+template <int L, int NT, int TW_LDS>
+struct TwCopy {
+  static constexpr int N = TW_LDS ? (L + NT - 1) / NT : 1;
+  float2 r[N];
+  __device__ __forceinline__ void issue(const float2* __restrict__ glob, unsigned tid) {
+    if constexpr (TW_LDS) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const unsigned t = tid + (unsigned)(i * NT);
+        if (L % NT == 0 || t < (unsigned)L) r[i] = glob[t];
+      }
+    }
+  }
+  __device__ __forceinline__ const float2* commit(float2* lds_tw, const float2* glob, unsigned tid) {
+    if constexpr (TW_LDS) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const unsigned t = tid + (unsigned)(i * NT);
+        if (L % NT == 0 || t < (unsigned)L) lds_tw[t] = r[i];
+      }
+      return lds_tw;
+    } else {
+      return glob;
+    }
+  }
+};
 
 struct ImgMeta {
   int m, n;            // m' (rows), n' (columns)
@@ -342,10 +379,14 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // for the halo line.  The column pass leaves the spectra in row blocks of
 // rb rows (entry (i, kx) at (i / rb) rb nbc + kx rb + i mod rb, nbc = nb C),
 // rb a multiple of RT: the own rows are RT consecutive rows of one block (the
-// whole block when rb = RT).  All loads are issued first.
-template <int L, int RT, bool HALO = true, int NT = kNTR>
+// whole block when rb = RT).  All loads are issued first; `extra` issues the
+// caller's own loads after them, before the first wait.
+struct NoExtraLoads {
+  __device__ __forceinline__ void operator()() const {}
+};
+template <int L, int RT, bool HALO = true, int NT = kNTR, class Extra = NoExtraLoads>
 __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
-                                            int nh, int nb, int C, int logC, int rb) {
+                                            int nh, int nb, int C, int logC, int rb, Extra extra = Extra()) {
   constexpr int LS = lstride(L);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
   constexpr int NQ = (RT * NBC_MAX + NT - 1) / NT;
@@ -382,6 +423,8 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
       hb[k] = sin2[2 * (bb + (unsigned)kx * rbu)];
     }
   }
+  // more loads of the caller, in flight with the spectra
+  extra();
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     if (dst[k] >= 0) {
@@ -495,7 +538,7 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
     if (l <= nr && l >= 1) buf[(l - 1) * LS + lpad(j)] = wreg[k];
   }
   __syncthreads();
-  fft_lines<L, false, NT, RT>(buf, nr, tw);
+  fft_lines<L, false, NT, RT, kEarlyTwRow>(buf, nr, tw);
   split_store<L, RT, NT>(sout, buf, M, r0, nr, nh, nb, C, logC, nt);
 }
 
@@ -519,8 +562,11 @@ __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, i
   const int C = mt.C, logC = mt.logC, nh = mt.nh, nb = mt.nb;
   float* __restrict__ yt = a.yt + mt.px;
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, kNTR>(lds + (RT + 1) * LS, a.tw + mt.twr);
-  gather_rows<L, RT, false>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
+  const float2* tw_glob = a.tw + mt.twr;
+  TwCopy<L, kNTR, kTwLdsRow> twc;
+  gather_rows<L, RT, false>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb,
+                            [&]() { twc.issue(tw_glob, tid); });
+  const float2* tw = twc.commit(lds + (RT + 1) * LS, tw_glob, tid);
   float yo[KP];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -528,7 +574,7 @@ __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, i
     if (l >= 1 && l <= nr) yo[k] = yt[(unsigned)((r0 + l - 1) * L + j)];
   }
   __syncthreads();
-  fft_lines<L, true, kNTR, RT>(buf, nr, tw);
+  fft_lines<L, true, kNTR, RT, kEarlyTwRow>(buf, nr, tw);
   // z-step on own row r = l - 1
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -558,7 +604,7 @@ __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, i
   }
   __syncthreads();
   const int npl = (nr + 1) >> 1;
-  fft_lines<L, false, kNTR, (RT + 1) / 2>(buf, npl, tw);
+  fft_lines<L, false, kNTR, (RT + 1) / 2, kEarlyTwRow>(buf, npl, tw);
   float2* __restrict__ sout2 = reinterpret_cast<float2*>(a.spec_out + mt.sp);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
@@ -628,7 +674,10 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   float* __restrict__ x_out = store_x ? a.x_out + mt.px : nullptr;
   float2* __restrict__ u_out = (GEN && a.u_out) ? a.u_out + mt.px : nullptr;
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, NT>(lds + (RT + 1) * LS, a.tw + mt.twr);
+  float2* lds_tw = lds + (RT + 1) * LS;
+  const float2* tw_glob = a.tw + mt.twr;
+  TwCopy<L, NT, kTwLdsRow> twc;
+  const float2* tw = tw_glob;
   const float mu = a.mu[img];
   const float tau = a.lam[img] / mu;
   const float tau2 = tau * tau;
@@ -638,12 +687,16 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   float rd = 0.f, rv = 0.f, rz = 0.f;
 
   if (!GEN || a.mode == ROW_ITER || uonly) {
-    gather_rows<L, RT, true, NT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb);
+    float2 dd[KP];
+    float yo[KP];
+    // the twiddle table's reads travel with the spectra; the state loads
+    // follow the inverse transform (issued before it, they slowed one 1024^2
+    // image's row pass by 5% even when every wave's spectra had arrived)
+    gather_rows<L, RT, true, NT>(a.spec_in + mt.sp, buf, M, r0, nr, nh, nb, C, logC, mt.rb,
+                                 [&]() { twc.issue(tw_glob, tid); });
+    tw = twc.commit(lds_tw, tw_glob, tid);
     __syncthreads();
-#if DCV_EARLY_STATE
-    // state loads for the epilogue, issued before the transform
-    float2 dd[KP];
-    float yo[KP];
+    fft_lines<L, true, NT, RT + 1, kEarlyTwRow>(buf, nr + 1, tw);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const int l = PM::row(k, tid), j = PM::col(k, tid);
@@ -653,21 +706,6 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
         if (l >= 1) yo[k] = ld_in<kNtLdRowState>(yt + pix);
       }
     }
-    fft_lines<L, true, NT, RT + 1>(buf, nr + 1, tw);
-#else
-    fft_lines<L, true, NT, RT + 1>(buf, nr + 1, tw);
-    float2 dd[KP];
-    float yo[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int l = PM::row(k, tid), j = PM::col(k, tid);
-      if (l <= nr) {
-        const unsigned pix = (unsigned)(wrapi(r0 - 1 + l, M) * L + j);
-        dd[k] = ld_in<kNtLdRowState>(d_in + pix);
-        if (l >= 1) yo[k] = ld_in<kNtLdRowState>(yt + pix);
-      }
-    }
-#endif
 
     // epilogue: z-step, TV prox, dual update for tile rows 0..nr
 #pragma unroll
@@ -710,6 +748,8 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
   } else {
     // ROW_STATE: start from a stored state (v, d, ytilde); d is rescaled by
     // dscale (penalty update of eq. (varying_penalty))
+    twc.issue(tw_glob, tid);
+    tw = twc.commit(lds_tw, tw_glob, tid);
     const float ds = a.dscale ? a.dscale[img] : 1.f;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
@@ -873,7 +913,7 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
   constexpr int NQ = ColLoad<L, NT>::NQ;
   const long long base = mt.sp + (long long)blk * L * C;
   __syncthreads();
-  fft_lines<L, false, NT, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, false, NT, 2 * C, kEarlyTwCol>(buf, 2 * C, tw);
   const float scale = 1.0f / ((float)L * (float)mt.n);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
@@ -901,7 +941,7 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
     }
   }
   __syncthreads();
-  fft_lines<L, true, NT, 2 * C>(buf, 2 * C, tw);
+  fft_lines<L, true, NT, 2 * C, kEarlyTwCol>(buf, 2 * C, tw);
   // output in the row-block layout the row pass reads (runs of rt rows)
   float4* __restrict__ sout = a.spec_out + mt.sp + (unsigned)(blk * C * mt.rb);
   const unsigned nbc = (unsigned)(mt.nb * C);
@@ -926,7 +966,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
   constexpr int C = c_for(L);
   const ImgMeta mt = a.meta[img];
   float2* buf = lds;
-  const float2* tw = twiddle_table<L, NT>(lds + 2 * C * lstride(L), a.tw + mt.twc);
+  const float2* tw = twiddle_table<L, NT, kTwLdsCol>(lds + 2 * C * lstride(L), a.tw + mt.twc);
   ColLoad<L, NT> r;
   col_load<L, NT>(a, mt, blk, r);
   col_fill<L, NT>(r, buf);
