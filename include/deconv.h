@@ -151,6 +151,15 @@ typedef struct {
                            iteration); 0: never (default: on MI355X the
                            two-pass kernels are as fast for one 72^2 image
                            and faster for batches of small images). */
+  int32_t separable_blur; /* 1 (default): the column pass of an image whose
+                           blur kernel is the outer product of two 1-D kernels
+                           (to within 1e-6 of its largest tap: box and
+                           Gaussian blurs) takes the blur spectrum as the
+                           product of their 1-D spectra, U(ky) V(kx), computed
+                           at setup, instead of reading the stored 2-D half
+                           spectrum (one 8-byte value per frequency and
+                           iteration less HBM traffic); 0: always the stored
+                           spectrum.  Results agree to rounding. */
 } deconv_options;
 
 typedef struct {
@@ -296,6 +305,12 @@ deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out);
    tile (512 or 1024), out[2] = threads per long column tile (256 or 512),
    out[3] = 1 if the plan runs the whole-image-in-LDS path (small_images). */
 deconv_status deconv_plan_tiles(deconv_plan p, int32_t* out);
+
+/* Which images' column passes take the blur spectrum as the product of 1-D
+   spectra (deconv_options.separable_blur): out[b] = 1 or 0, host array
+   [batch], as set by the last run or state import (0 before any).  Host
+   call; synchronises the plan's stream. */
+deconv_status deconv_plan_separable(deconv_plan p, int32_t* out);
 
 const char* deconv_status_str(deconv_status s);
 

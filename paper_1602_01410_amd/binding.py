@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("warm_tau", ctypes.c_float), ("channels", ctypes.c_int32),
                 ("spectra_hint", ctypes.c_int32), ("row_tiles", ctypes.c_int32),
                 ("row_threads", ctypes.c_int32), ("col_threads", ctypes.c_int32),
-                ("small_images", ctypes.c_int32)]
+                ("small_images", ctypes.c_int32), ("separable_blur", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -55,7 +55,7 @@ EXPORTS = ("deconv_options_default", "deconv_plan_workspace_size", "deconv_plan_
            "deconv_plan_destroy", "deconv_admm_run", "deconv_admm_continue", "deconv_state_export",
            "deconv_state_import", "deconv_admm_backward", "deconv_plan_run_id", "deconv_blur_spectrum",
            "deconv_fft2", "deconv_plan_kernel_times", "deconv_plan_bwd_kernel_times", "deconv_plan_schedule",
-           "deconv_plan_tiles",
+           "deconv_plan_tiles", "deconv_plan_separable",
            "deconv_status_str",
            "deconv_admm_run_static")
 
@@ -91,6 +91,7 @@ def lib():
         L.deconv_plan_bwd_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
         L.deconv_plan_schedule.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         L.deconv_plan_tiles.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.deconv_plan_separable.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         L.deconv_status_str.argtypes = [I32]
         L.deconv_status_str.restype = ctypes.c_char_p
         for f in EXPORTS:
@@ -253,6 +254,13 @@ class Plan:
         long column tile, 1 if the whole-image-in-LDS path runs) in use."""
         out = (ctypes.c_int32 * 4)()
         _check(lib().deconv_plan_tiles(self.handle, out), "tiles")
+        return tuple(out)
+
+    def separable(self):
+        """Per image: 1 if the column pass takes the blur spectrum as the
+        product of 1-D spectra (separable_blur), as set by the last run."""
+        out = (ctypes.c_int32 * self.batch)()
+        _check(lib().deconv_plan_separable(self.handle, out), "separable")
         return tuple(out)
 
     def kernel_times(self):

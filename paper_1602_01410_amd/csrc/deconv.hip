@@ -210,6 +210,8 @@ struct deconv_plan_s {
   float4* specB = nullptr;
   float2* hh = nullptr;
   float* tab = nullptr;
+  float2* hsep = nullptr;     // separable blurs: 1-D spectra U, V (offsets of tab)
+  int* sep = nullptr;         // per image: 1 = the column pass uses U V
   float2* tw = nullptr;
   double* partials = nullptr;
   int* done = nullptr;
@@ -289,7 +291,7 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
       off_part, off_done, off_nonf, off_itd, off_stopbuf, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
-      off_dscale, off_small;
+      off_dscale, off_small, off_hsep, off_sep;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
       off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64, off_adj_T;
   size_t total;
@@ -323,6 +325,7 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     if (opt->col_threads != 0 && opt->col_threads != kNTC && opt->col_threads != kNTCWide)
       return DECONV_ERR_INVALID_ARG;
     if (opt->small_images < 0 || opt->small_images > 1) return DECONV_ERR_INVALID_ARG;
+    if (opt->separable_blur < 0 || opt->separable_blur > 1) return DECONV_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
       const deconv_image_desc& f = desc[b - b % opt->channels];
       if (desc[b].height != f.height || desc[b].width != f.width || desc[b].ksize != f.ksize)
@@ -438,6 +441,8 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   lay.off_mu = take(sizeof(float) * B);
   lay.off_dscale = take(sizeof(float) * B);
   lay.off_small = take(sizeof(int) * B);
+  lay.off_hsep = take(sizeof(float2) * tab);
+  lay.off_sep = take(sizeof(int) * B);
   const int ck = p->opt.ckpt_every;
   if (ck > 0) {
     const int nck = (p->opt.max_iters + ck - 1) / ck + 1;
@@ -652,6 +657,7 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->row_threads = 0;
   opt->col_threads = 0;
   opt->small_images = 0;
+  opt->separable_blur = 1;
   return DECONV_OK;
 }
 
@@ -741,6 +747,8 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   p->mu_cur = at<float>(w, lay.off_mu);
   p->dscale = at<float>(w, lay.off_dscale);
   p->d_small = at<int>(w, lay.off_small);
+  p->hsep = at<float2>(w, lay.off_hsep);
+  p->sep = at<int>(w, lay.off_sep);
   if (p->opt.ckpt_every > 0) {
     p->ck_yt = at<float>(w, lay.off_ck_yt);
     p->ck_v = at<float2>(w, lay.off_ck_v);
@@ -805,6 +813,8 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
       hipMemsetAsync(p->specA, 0, sizeof(float4) * p->total_sp, s) != hipSuccess ||
       hipMemsetAsync(p->specB, 0, sizeof(float4) * p->total_sp, s) != hipSuccess ||
       hipMemsetAsync(p->done, 0, sizeof(int) * batch, s) != hipSuccess ||
+      // no blur yet: the autotuner's passes read the stored spectrum
+      hipMemsetAsync(p->sep, 0, sizeof(int) * batch, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(DECONV_ERR_HIP);
   // the whole-image-in-LDS path (asked for with opt.small_images = 1) takes
@@ -877,6 +887,9 @@ static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* ful
   if (pack) {
     hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
     HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(separable_psf_kernel, dim3(B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, p->hsep, p->sep,
+                       p->opt.separable_blur);
+    HIPCHK(hipGetLastError());
   }
   std::vector<float2> hs(B);
   HIPCHK(hipMemcpyAsync(hs.data(), p->hsum, sizeof(float2) * B, hipMemcpyDeviceToHost, s));
@@ -924,6 +937,8 @@ static ColArgs col_args(deconv_plan_s* p, const float* mu) {
   a.spec_out = p->specB;
   a.hh = p->hh;
   a.tab = p->tab;
+  a.hsep = p->hsep;
+  a.sep = p->sep;
   a.mu = mu;
   a.tw = p->tw;
   a.done = p->done;
@@ -1228,6 +1243,13 @@ extern "C" deconv_status deconv_plan_tiles(deconv_plan p, int32_t* out) {
   out[1] = p->wide_row ? kNTRWide : kNTR;
   out[2] = p->wide_col ? kNTCWide : kNTC;
   out[3] = p->small ? 1 : 0;
+  return DECONV_OK;
+}
+
+extern "C" deconv_status deconv_plan_separable(deconv_plan p, int32_t* out) {
+  if (!p || !out) return DECONV_ERR_INVALID_ARG;
+  HIPCHK(hipMemcpyAsync(out, p->sep, sizeof(int32_t) * p->batch, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
   return DECONV_OK;
 }
 

@@ -220,6 +220,8 @@ struct ColArgs {
   float4* spec_out;
   const float2* hh;          // blur half spectrum, tiled like the spectra (float2)
   const float* tab;          // per image: |D_v|^2[m'] then |D_h|^2[nb*C]
+  const float2* hsep;        // separable blurs: U[m'] then V[nb*C] per image (offsets of tab)
+  const int* sep;            // per image: 1 = H(ky, kx) = U(ky) V(kx), nullable
   const float* mu;
   const float2* tw;
   float4* spec_store;        // (Y, X) per frequency for the backward, nullable
@@ -861,30 +863,48 @@ struct ColLoad {
   static constexpr int C = c_for(L);
   static constexpr int NQ = (L * C + NT - 1) / NT;
   float4 g[NQ];
-  float2 Hk[NQ];
-  float dsum[NQ];
+  float2 Hk[NQ];   // blur spectrum, or U(ky) for a separable blur
+  float dv[NQ];    // |D_v|^2(ky)
+  // a thread's column c = tid mod C is the same for all its entries (NT is
+  // a multiple of C): one V(kx) and one |D_h|^2(kx) per thread
+  float2 Hv;       // V(kx) for a separable blur
+  float dh;
+  static_assert(NT % C == 0, "a thread keeps one column of its tile");
 };
 
-// issue every load of tile (img, blk)
+// issue every load of tile (img, blk).  A separable blur (sep) takes its
+// spectrum as the product of the two 1-D spectra, U(ky) V(kx): per image m'
+// + nb C values that stay in the caches, instead of one stored value per
+// frequency.
 template <int L, int NT>
-__device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, int blk, ColLoad<L, NT>& r) {
+__device__ __forceinline__ void col_load(const ColArgs& a, const ImgMeta& mt, int blk, bool sep,
+                                         ColLoad<L, NT>& r) {
   constexpr int C = c_for(L);
   constexpr int NQ = ColLoad<L, NT>::NQ;
   const long long base = mt.sp + (long long)blk * L * C;
   const float4* __restrict__ sin = a.spec_in + base;
   const float2* __restrict__ hh = a.hh + mt.hh + (long long)blk * L * C;
+  const float2* __restrict__ hu = a.hsep + mt.tab;
+  const float2* __restrict__ hv = hu + L;
   const float* __restrict__ dv2 = a.tab + mt.tab;
   const float* __restrict__ dh2 = dv2 + L;
+  // (products and sums of these values are formed where they are used,
+  // after the forward transform: formed here they would wait on every load
+  // in flight)
+  const int kx = blk * C + (int)(threadIdx.x % C);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = threadIdx.x + k * NT;
     if (q < L * C) {
-      const int ky = q / C, c = q - ky * C;
+      const int ky = q / C;
       r.g[k] = ld_in<kNtLdCol>(sin + q);
-      r.Hk[k] = ld_in<kNtLdCol>(hh + q);
-      r.dsum[k] = dh2[blk * C + c] + dv2[ky];
+      if (sep) r.Hk[k] = hu[ky];
+      else r.Hk[k] = ld_in<kNtLdCol>(hh + q);
+      r.dv[k] = dv2[ky];
     }
   }
+  if (sep) r.Hv = hv[kx];
+  r.dh = dh2[kx];
 }
 
 // the column spectra into the LDS lines (Y in line 2c, mu G in line 2c+1)
@@ -907,7 +927,8 @@ __device__ __forceinline__ void col_fill(const ColLoad<L, NT>& r, float2* buf) {
 // the caller has filled the lines (not yet synchronised)
 template <int L, int NT>
 __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta& mt, int blk, float muv,
-                                                const float2* Hk, const float* dsum, float2* buf, const float2* tw) {
+                                                const float2* Hk, float2 Hv, bool sep, const float* dv, float dh,
+                                                float2* buf, const float2* tw) {
   constexpr int C = c_for(L);
   constexpr int LS = lstride(L);
   constexpr int NQ = ColLoad<L, NT>::NQ;
@@ -925,12 +946,12 @@ __device__ __forceinline__ void col_solve_store(const ColArgs& a, const ImgMeta&
       const float2 G = buf[(2 * c + 1) * LS + lpad(ky)];
       float2 X = make_float2(0.f, 0.f), Q = X;
       if (kx < mt.nh) {
-        const float2 H = Hk[k];
+        const float2 H = sep ? cmul(Hk[k], Hv) : Hk[k];
         const float h2 = H.x * H.x + H.y * H.y;
         // x-step: (conj(H) Y + G) / (|H|^2 + mu |D|^2); warm start (eq. (ini_x)):
         // conj(H) Y / (|H|^2 + tau)
         const float2 Gk = a.warm ? make_float2(0.f, 0.f) : G;
-        const float den = a.warm ? h2 + a.warm_tau : h2 + muv * dsum[k];
+        const float den = a.warm ? h2 + a.warm_tau : h2 + muv * (dh + dv[k]);
         const float inv = scale * frcp(den);
         X = make_float2((H.x * Y.x + H.y * Y.y + Gk.x) * inv, (H.x * Y.y - H.y * Y.x + Gk.y) * inv);
         Q = cmul(H, X);
@@ -968,9 +989,10 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int img, int blk, flo
   float2* buf = lds;
   const float2* tw = twiddle_table<L, NT, kTwLdsCol>(lds + 2 * C * lstride(L), a.tw + mt.twc);
   ColLoad<L, NT> r;
-  col_load<L, NT>(a, mt, blk, r);
+  const bool sep = a.sep != nullptr && a.sep[img] != 0;
+  col_load<L, NT>(a, mt, blk, sep, r);
   col_fill<L, NT>(r, buf);
-  col_solve_store<L, NT>(a, mt, blk, a.mu[img], r.Hk, r.dsum, buf, tw);
+  col_solve_store<L, NT>(a, mt, blk, a.mu[img], r.Hk, r.Hv, sep, r.dv, r.dh, buf, tw);
 }
 
 template <int L, int NT = kNTC>

@@ -80,6 +80,78 @@ __global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ 
   }
 }
 
+// Separable blurs.  If the (2b+1)^2 kernel of an image is the outer product
+// h(p, q) = u(p) v(q) (to within 1e-6 of its largest tap), its spectrum is
+// H(ky, kx) = U(ky) V(kx) with the 1-D spectra
+//   U(ky) = sum_p u(p) exp(-2 pi i ky p / m'),  V(kx) = sum_q v(q) exp(-2 pi i kx q / n'),
+// p, q = -b..b (the kernel centred at the origin, as embed_psf_kernel places
+// it).  One workgroup per image: pivot at the largest |h|, u = its column,
+// v = its row over the pivot; the rank-one test; U and V by direct FP64
+// sums.  out: per image U[m'] then V[nb C] at the |D|^2 table's offset
+// (tab); sep[img] = 1 when used (enable and the test passes), else 0.
+constexpr int kSepMaxK = 129;
+__global__ void __launch_bounds__(kNT) separable_psf_kernel(const ImgMeta* meta, const float* __restrict__ h,
+                                                           const long long* hoff, float2* out, int* sep,
+                                                           int enable) {
+  const int img = blockIdx.x;
+  const ImgMeta mt = meta[img];
+  const int b = mt.b, K = 2 * b + 1;
+  const float* __restrict__ hk = h + hoff[img];
+  __shared__ double u[kSepMaxK], v[kSepMaxK];
+  __shared__ int pivot, ok;
+  if (threadIdx.x == 0) {
+    ok = enable && K <= kSepMaxK;
+    int best = 0;
+    for (int t = 1; ok && t < K * K; ++t)
+      if (fabsf(hk[t]) > fabsf(hk[best])) best = t;
+    pivot = best;
+    ok = ok && hk[best] != 0.f;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (threadIdx.x == 0) sep[img] = 0;
+    return;
+  }
+  const int pr = pivot / K, pc = pivot % K;
+  const double hp = hk[pivot];
+  for (int t = threadIdx.x; t < K; t += blockDim.x) {
+    u[t] = hk[t * K + pc];
+    v[t] = (double)hk[pr * K + t] / hp;
+  }
+  __syncthreads();
+  const double tol = 1e-6 * fabs(hp);
+  for (int t = threadIdx.x; t < K * K; t += blockDim.x)
+    if (fabs((double)hk[t] - u[t / K] * v[t % K]) > tol) ok = 0;
+  __syncthreads();
+  if (!ok) {
+    if (threadIdx.x == 0) sep[img] = 0;
+    return;
+  }
+  float2* U = out + mt.tab;
+  float2* V = U + mt.m;
+  const int nv = mt.nb * mt.C;
+  for (int t = threadIdx.x; t < mt.m + nv; t += blockDim.x) {
+    const bool isu = t < mt.m;
+    const int k = isu ? t : t - mt.m;
+    const int len = isu ? mt.m : mt.n;
+    const double* w = isu ? u : v;
+    double re = 0.0, im = 0.0;
+    if (isu || k < mt.nh) {
+      for (int p = -b; p <= b; ++p) {
+        // exp(-2 pi i k p / len) with the phase reduced exactly
+        long long r = ((long long)k * p) % len;
+        if (r < 0) r += len;
+        double sn, cs;
+        sincospi(2.0 * (double)r / (double)len, &sn, &cs);
+        re += w[p + b] * cs;
+        im -= w[p + b] * sn;
+      }
+    }
+    (isu ? U[k] : V[k]) = make_float2((float)re, (float)im);
+  }
+  if (threadIdx.x == 0) sep[img] = 1;
+}
+
 // copy the spectrum columns kx < nh into the tiled half layout
 __global__ void pack_half_kernel(const ImgMeta* meta, const float2* __restrict__ grid,
                                  const long long* goff, float2* hh) {
