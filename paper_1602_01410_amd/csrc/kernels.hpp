@@ -395,7 +395,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
   constexpr int NH = (NBC_MAX + NT - 1) / NT;
   const float2* __restrict__ sin2 = reinterpret_cast<const float2*>(sin);
   float4 g[NQ];
-  int dst[NQ];
+  int dst[NQ];   // (line << 12) | kx of each load, -1 for none
   float2 ha[NH], hb[NH];
   const int ia = r0 == 0 ? M - 1 : r0 - 1;
   const int ib = r0 + nr == M ? 0 : r0 + nr;
@@ -412,7 +412,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
     dst[k] = -1;
     if (l < nr && kx < nh) {
       g[k] = ld_in<kNtLdRowSpec>(blkp + ((unsigned)kx * rbu + (unsigned)l));
-      dst[k] = l * LS + kx;
+      dst[k] = (l << 12) | kx;
     }
   }
   const unsigned ba = (unsigned)(ia / rb) * rbu * nbc + (unsigned)(ia % rb);
@@ -430,7 +430,7 @@ __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, floa
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     if (dst[k] >= 0) {
-      const int l = dst[k] / LS, kx = dst[k] - l * LS;
+      const int l = dst[k] >> 12, kx = dst[k] & 4095;
       const float4 v = g[k];
       float2* line = buf + l * LS;
       line[lpad(kx)] = make_float2(v.x - v.w, v.y + v.z);
