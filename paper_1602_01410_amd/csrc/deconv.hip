@@ -863,32 +863,59 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
 static std::atomic<uint64_t> g_run_id{0};
 static uint64_t new_run_id() { return ++g_run_id; }
 
-// H^ of every image into the grid in specB (free between calls: the column
-// pass output is rebuilt by every prologue); pack = also store the half
-// spectrum the passes read (deconv_blur_spectrum leaves it alone)
+// H^ of every image, by direct sums over the taps (one launch for the batch)
+// or, for kernels wider than kBlurMaxK, by 2-D FFTs of the embedded kernels
+// in the grid in specB (free between calls: the column pass output is
+// rebuilt by every prologue): full_out = the whole spectra (for
+// deconv_blur_spectrum); pack = the half spectrum the passes read and the
+// separable factors (deconv_blur_spectrum leaves them alone)
 static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out, bool pack = true) {
   hipStream_t s = p->stream;
-  float2* grid = reinterpret_cast<float2*>(p->specB);
   const int B = p->batch;
-  int gx = 64;
-  HIPCHK(hipMemsetAsync(grid, 0, sizeof(float4) * (size_t)p->total_sp, s));
-  hipLaunchKernelGGL(embed_psf_kernel, dim3(B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, grid, p->goff);
-  HIPCHK(hipGetLastError());
-  for (int b = 0; b < B; ++b) {
-    const ImgMeta& m = p->meta[b];
-    float2* g = grid + 2 * m.sp;
-    HIPCHK(launch_fft_rows(m.n, g, m.m, p->tw + m.twr, 0, s));
-    HIPCHK(launch_fft_cols(m.m, g, m.n, 1, p->tw + m.twc, 0, s));
-    if (full_out)
-      HIPCHK(hipMemcpyAsync(reinterpret_cast<float2*>(full_out) + m.px, g, sizeof(float2) * m.m * m.n,
-                            hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(p->hsum + b, g, sizeof(float2), hipMemcpyDeviceToDevice, s));
+  int maxk = 0, maxcol = 0, maxout = 0;
+  for (const ImgMeta& m : p->meta) {
+    maxk = std::max(maxk, 2 * m.b + 1);
+    maxcol = std::max(maxcol, m.nb * m.C);
+    maxout = std::max(maxout, m.m + m.nb * m.C);
+  }
+  if (maxk <= kBlurMaxK) {
+    if (full_out) {
+      int maxn = 0;
+      for (const ImgMeta& m : p->meta) maxn = std::max(maxn, m.n);
+      hipLaunchKernelGGL(blur_half_kernel, dim3((maxn + kBlurCols - 1) / kBlurCols, B), dim3(kNT), 0, s,
+                         p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, reinterpret_cast<float2*>(full_out));
+      HIPCHK(hipGetLastError());
+    }
+    if (pack) {
+      hipLaunchKernelGGL(blur_half_kernel, dim3((maxcol + kBlurCols - 1) / kBlurCols, B), dim3(kNT), 0, s,
+                         p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, nullptr);
+      HIPCHK(hipGetLastError());
+    }
+  } else {
+    // whole spectra by 2-D FFTs of the embedded kernels
+    float2* grid = reinterpret_cast<float2*>(p->specB);
+    int gx = 64;
+    HIPCHK(hipMemsetAsync(grid, 0, sizeof(float4) * (size_t)p->total_sp, s));
+    hipLaunchKernelGGL(embed_psf_kernel, dim3(B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, grid, p->goff);
+    HIPCHK(hipGetLastError());
+    for (int b = 0; b < B; ++b) {
+      const ImgMeta& m = p->meta[b];
+      float2* g = grid + 2 * m.sp;
+      HIPCHK(launch_fft_rows(m.n, g, m.m, p->tw + m.twr, 0, s));
+      HIPCHK(launch_fft_cols(m.m, g, m.n, 1, p->tw + m.twc, 0, s));
+      if (full_out)
+        HIPCHK(hipMemcpyAsync(reinterpret_cast<float2*>(full_out) + m.px, g, sizeof(float2) * m.m * m.n,
+                              hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(p->hsum + b, g, sizeof(float2), hipMemcpyDeviceToDevice, s));
+    }
+    if (pack) {
+      hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
+      HIPCHK(hipGetLastError());
+    }
   }
   if (pack) {
-    hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(separable_psf_kernel, dim3(B), dim3(kNT), 0, s, p->d_meta, h, p->hoff, p->hsep, p->sep,
-                       p->opt.separable_blur);
+    hipLaunchKernelGGL(separable_psf_kernel, dim3((maxout + kNT - 1) / kNT, B), dim3(kNT), 0, s, p->d_meta, h,
+                       p->hoff, p->tw, p->hsep, p->sep, p->opt.separable_blur);
     HIPCHK(hipGetLastError());
   }
   std::vector<float2> hs(B);

@@ -80,76 +80,159 @@ __global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ 
   }
 }
 
+// Blur half spectrum by direct summation (setup).  For the (2b+1)^2 kernel
+// centred at the origin (as embed_psf_kernel places it),
+//   H(ky, kx) = sum_p w_m^(ky p) T(p, kx),  T(p, kx) = sum_q h(p, q) w_n^(kx q),
+// p, q = -b..b, w_L = exp(-2 pi i / L) read from the twiddle tables (phase
+// indices reduced exactly).  One workgroup per image and block of kBlurCols
+// spectrum columns: T of its columns in LDS, then every row ky; written in
+// the tiled half layout the column pass reads (zero past nh), or, with
+// full, as the whole m' x n' spectrum (row-major at the image's pixel
+// offset); H(0, 0) into hsum.  Kernels up to kBlurMaxK taps a side; FP32
+// sums of K terms.
+constexpr int kBlurCols = 32;
+constexpr int kBlurMaxK = 65;
+__global__ void __launch_bounds__(kNT) blur_half_kernel(const ImgMeta* meta, const float* __restrict__ h,
+                                                       const long long* hoff, const float2* __restrict__ tw,
+                                                       float2* hh, float2* hsum, float2* full) {
+  const int img = blockIdx.y;
+  const ImgMeta mt = meta[img];
+  const int ncol = full ? mt.n : mt.nb * mt.C;
+  const int nval = full ? mt.n : mt.nh;   // columns with values (zero past them)
+  const int kx0 = blockIdx.x * kBlurCols;
+  if (kx0 >= ncol) return;
+  const int b = mt.b, K = 2 * b + 1;
+  const float* __restrict__ hk = h + hoff[img];
+  const float2* __restrict__ twn = tw + mt.twr;
+  const float2* __restrict__ twm = tw + mt.twc;
+  __shared__ float2 T[kBlurMaxK * kBlurCols];
+  for (int t = threadIdx.x; t < K * kBlurCols; t += kNT) {
+    const int p = t / kBlurCols, kx = kx0 + t % kBlurCols;
+    float re = 0.f, im = 0.f;
+    if (kx < nval) {
+      // r = kx (q - b) mod n', stepped by kx
+      int r = (int)(((long long)kx * (mt.n - b)) % mt.n);
+      for (int q = 0; q < K; ++q) {
+        const float2 w = twn[r];
+        const float hv = hk[p * K + q];
+        re = fmaf(hv, w.x, re);
+        im = fmaf(hv, w.y, im);
+        r += kx;
+        if (r >= mt.n) r -= mt.n;
+      }
+    }
+    T[t] = make_float2(re, im);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < mt.m * kBlurCols; t += kNT) {
+    const int ky = t / kBlurCols, c = t % kBlurCols, kx = kx0 + c;
+    if (kx >= ncol) continue;
+    float re = 0.f, im = 0.f;
+    if (kx < nval) {
+      int r = (int)(((long long)ky * (mt.m - b)) % mt.m);
+      for (int p = 0; p < K; ++p) {
+        const float2 w = twm[r];
+        const float2 tv = T[p * kBlurCols + c];
+        re = fmaf(tv.x, w.x, fmaf(-tv.y, w.y, re));
+        im = fmaf(tv.x, w.y, fmaf(tv.y, w.x, im));
+        r += ky;
+        if (r >= mt.m) r -= mt.m;
+      }
+    }
+    if (full) full[mt.px + (long long)ky * mt.n + kx] = make_float2(re, im);
+    else hh[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))] = make_float2(re, im);
+    if (kx == 0 && ky == 0) hsum[img] = make_float2(re, im);
+  }
+}
+
 // Separable blurs.  If the (2b+1)^2 kernel of an image is the outer product
 // h(p, q) = u(p) v(q) (to within 1e-6 of its largest tap), its spectrum is
 // H(ky, kx) = U(ky) V(kx) with the 1-D spectra
-//   U(ky) = sum_p u(p) exp(-2 pi i ky p / m'),  V(kx) = sum_q v(q) exp(-2 pi i kx q / n'),
+//   U(ky) = sum_p u(p) w_m^(ky p),  V(kx) = sum_q v(q) w_n^(kx q),
 // p, q = -b..b (the kernel centred at the origin, as embed_psf_kernel places
-// it).  One workgroup per image: pivot at the largest |h|, u = its column,
-// v = its row over the pivot; the rank-one test; U and V by direct FP64
-// sums.  out: per image U[m'] then V[nb C] at the |D|^2 table's offset
-// (tab); sep[img] = 1 when used (enable and the test passes), else 0.
-constexpr int kSepMaxK = 129;
+// it; w_L from the twiddle tables).  Pivot at the largest |h| (first on ties),
+// u = its column, v = its row over the pivot; the rank-one test; then U and V.
+// Grid: (blocks of kNT outputs, images); each workgroup repeats the test and
+// writes its share of U[m'] then V[nb C] at the |D|^2 table's offset (tab);
+// sep[img] = 1 when used (enable and the test passes), else 0.
+constexpr int kSepMaxK = 65;
 __global__ void __launch_bounds__(kNT) separable_psf_kernel(const ImgMeta* meta, const float* __restrict__ h,
-                                                           const long long* hoff, float2* out, int* sep,
-                                                           int enable) {
-  const int img = blockIdx.x;
+                                                           const long long* hoff, const float2* __restrict__ tw,
+                                                           float2* out, int* sep, int enable) {
+  const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
+  const int nout = mt.m + mt.nb * mt.C;
+  if ((int)blockIdx.x * kNT >= nout) return;
   const int b = mt.b, K = 2 * b + 1;
   const float* __restrict__ hk = h + hoff[img];
-  __shared__ double u[kSepMaxK], v[kSepMaxK];
-  __shared__ int pivot, ok;
+  __shared__ float u[kSepMaxK], v[kSepMaxK];
+  __shared__ float best_v[kNT / 64];
+  __shared__ int best_i[kNT / 64];
+  __shared__ int ok;
+  const bool fits = enable && K <= kSepMaxK;
+  // pivot: largest |h|, smallest index on ties (wave maxima, then the waves)
+  float bv = -1.f;
+  int bi = 0x7fffffff;
+  for (int t = threadIdx.x; fits && t < K * K; t += kNT) {
+    const float a = fabsf(hk[t]);
+    if (a > bv) { bv = a; bi = t; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(bv, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  if ((threadIdx.x & 63) == 0) { best_v[threadIdx.x >> 6] = bv; best_i[threadIdx.x >> 6] = bi; }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    ok = enable && K <= kSepMaxK;
-    int best = 0;
-    for (int t = 1; ok && t < K * K; ++t)
-      if (fabsf(hk[t]) > fabsf(hk[best])) best = t;
-    pivot = best;
-    ok = ok && hk[best] != 0.f;
+    for (int w = 1; w < kNT / 64; ++w)
+      if (best_v[w] > bv || (best_v[w] == bv && best_i[w] < bi)) { bv = best_v[w]; bi = best_i[w]; }
+    best_i[0] = bi;
+    ok = fits && bv > 0.f;
   }
   __syncthreads();
   if (!ok) {
-    if (threadIdx.x == 0) sep[img] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) sep[img] = 0;
     return;
   }
+  const int pivot = best_i[0];
   const int pr = pivot / K, pc = pivot % K;
-  const double hp = hk[pivot];
-  for (int t = threadIdx.x; t < K; t += blockDim.x) {
+  const float hp = hk[pivot];
+  for (int t = threadIdx.x; t < K; t += kNT) {
     u[t] = hk[t * K + pc];
-    v[t] = (double)hk[pr * K + t] / hp;
+    v[t] = hk[pr * K + t] / hp;
   }
   __syncthreads();
-  const double tol = 1e-6 * fabs(hp);
-  for (int t = threadIdx.x; t < K * K; t += blockDim.x)
-    if (fabs((double)hk[t] - u[t / K] * v[t % K]) > tol) ok = 0;
+  const float tol = 1e-6f * fabsf(hp);
+  for (int t = threadIdx.x; t < K * K; t += kNT)
+    if (fabsf(hk[t] - u[t / K] * v[t % K]) > tol) ok = 0;
   __syncthreads();
   if (!ok) {
-    if (threadIdx.x == 0) sep[img] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) sep[img] = 0;
     return;
   }
-  float2* U = out + mt.tab;
-  float2* V = U + mt.m;
-  const int nv = mt.nb * mt.C;
-  for (int t = threadIdx.x; t < mt.m + nv; t += blockDim.x) {
+  const int t = blockIdx.x * kNT + threadIdx.x;
+  if (t < nout) {
     const bool isu = t < mt.m;
     const int k = isu ? t : t - mt.m;
     const int len = isu ? mt.m : mt.n;
-    const double* w = isu ? u : v;
-    double re = 0.0, im = 0.0;
+    const float* w = isu ? u : v;
+    const float2* __restrict__ twl = tw + (isu ? mt.twc : mt.twr);
+    float re = 0.f, im = 0.f;
     if (isu || k < mt.nh) {
-      for (int p = -b; p <= b; ++p) {
-        // exp(-2 pi i k p / len) with the phase reduced exactly
-        long long r = ((long long)k * p) % len;
-        if (r < 0) r += len;
-        double sn, cs;
-        sincospi(2.0 * (double)r / (double)len, &sn, &cs);
-        re += w[p + b] * cs;
-        im -= w[p + b] * sn;
+      int r = (int)(((long long)k * (len - b)) % len);
+      for (int p = 0; p < K; ++p) {
+        const float2 e = twl[r];
+        re = fmaf(w[p], e.x, re);
+        im = fmaf(w[p], e.y, im);
+        r += k;
+        if (r >= len) r -= len;
       }
     }
-    (isu ? U[k] : V[k]) = make_float2((float)re, (float)im);
+    (isu ? out[mt.tab + k] : out[mt.tab + mt.m + k]) = make_float2(re, im);
   }
-  if (threadIdx.x == 0) sep[img] = 1;
+  if (threadIdx.x == 0 && blockIdx.x == 0) sep[img] = 1;
 }
 
 // copy the spectrum columns kx < nh into the tiled half layout

@@ -1,8 +1,10 @@
-"""Separable blurs in the column pass: a blur kernel that is the outer
-product of two 1-D kernels enters the x-step of eq.
+"""Blur spectrum setup and separable blurs in the column pass.  A blur
+kernel that is the outer product of two 1-D kernels enters the x-step of eq.
 (dual_x_iter_resolved_boundaries) through the product of its 1-D spectra
-instead of the stored 2-D spectrum.  The images that take that path, and the
-results of both paths against the FP64 oracle and against each other."""
+instead of the stored 2-D spectrum: the images that take that path, and the
+results of both paths against the FP64 oracle and against each other.
+Kernels wider than 65 taps get their spectrum from FFTs rather than direct
+sums."""
 import numpy as np
 import pytest
 
@@ -65,3 +67,27 @@ def test_separable_matches_stored_spectrum(use_graph):
             assert np.array_equal(a["x"][k], b["x"][k])
         else:
             assert r <= 1e-5
+
+
+def test_wide_kernel_takes_fft_setup():
+    """Kernels wider than 65 taps get their spectrum from 2-D FFTs instead of
+    the direct sums (and never the separable path): the spectrum against the
+    oracle, then a run against the oracle."""
+    import torch
+    import oracle
+    from paper_1602_01410_amd import binding
+    kernels = [synth.gaussian_kernel(67, 9.0), synth.box_kernel(5)]
+    plan = binding.Plan([dict(height=192, width=256, ksize=k.shape[0]) for k in kernels])
+    h = torch.from_numpy(np.concatenate([k.astype(np.float32).ravel() for k in kernels])).cuda()
+    spec = plan.blur_spectrum(h).cpu().numpy().view(np.complex64).reshape(len(kernels), 192, 256)
+    for k, s in zip(kernels, spec):
+        ref = oracle.psf_spectrum(192, 256, k.astype(np.float32).astype(np.float64))
+        r = rel_l2(s, ref)
+        log("ksize %d spectrum rel_l2 %.3e" % (k.shape[0], r))
+        assert r <= 1e-6
+    p = synth.problem(192, 256, 67, "rect", "gauss", sigma=9.0, bsnr=50.0, lam=1e-3, mu=0.05, seed=91)
+    g = gpu_run([p], 30)
+    assert g["plan"].separable() == (0,)
+    r = oracle_run(p, 30)
+    assert_parity(g["x"][0], r["x"], what="ksize 67 x")
+    assert_parity(g["yt"][0], r["yt"], what="ksize 67 ytilde")
