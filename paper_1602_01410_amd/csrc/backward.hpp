@@ -89,7 +89,7 @@ template <int L>
 __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r0, float2* lds) {
   using PM = PixMap<L>;
   constexpr int RT = rt_for(L);
-  constexpr int LS = lstride(L);
+  constexpr int LS = row_lstride(L, RT);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;
   static_assert(KP <= 32, "observed flags of a thread's pixels are kept in one word");
   const unsigned tid = threadIdx.x;
@@ -131,7 +131,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
 #if !DCV_BWD_EARLY_STATE
     // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
     __syncthreads();
-    fft_lines<L, true, kNTR, RT + 1, kEarlyTwRow>(buf, nr + 1, tw);
+    fft_lines<L, true, kNTR, RT + 1, kEarlyTwRow, LS>(buf, nr + 1, tw);
 #endif
   }
   if (start) {
@@ -163,7 +163,7 @@ __device__ __forceinline__ void bwd_row_tile(const BwdRowArgs& a, int img, int r
   if (!start) {
     // finish reverse step: rb + i H rb on the own rows, rb on the halo rows
     __syncthreads();
-    fft_lines<L, true, kNTR, RT + 1, kEarlyTwRow>(buf, nr + 1, tw);
+    fft_lines<L, true, kNTR, RT + 1, kEarlyTwRow, LS>(buf, nr + 1, tw);
   }
 #endif
 

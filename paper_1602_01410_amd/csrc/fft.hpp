@@ -246,7 +246,7 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* 
 
 // ---------------------------------------------------------------------------
 // one Stockham pass over `nlines` lines of length L stored in LDS
-// (line q at buf + q * lstride(L)); NT threads cooperate, each takes up to
+// (line q at buf + q * LS, LS >= lstride(L)); NT threads cooperate, each takes up to
 // MAXB butterflies.  tw is the LDS table exp(-2 pi i t / L), t < L.
 // The caller must have synchronised after the last write of buf.
 // ---------------------------------------------------------------------------
@@ -254,13 +254,12 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int jm, const float2* 
 // passes a copy the compiler cannot see through).  With EARLY_TW the twiddle
 // reads are issued together with the data reads, before the barrier, so that
 // a table read from global memory waits on the barrier rather than after it.
-template <int L, int R, int NS, bool INV, int NT, int MAXLINES, bool EARLY_TW = false>
+template <int L, int R, int NS, bool INV, int NT, int MAXLINES, bool EARLY_TW = false, int LS = lstride(L)>
 __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const float2* tw,
                                               unsigned tid = threadIdx.x) {
   constexpr int NB = L / R;
   constexpr int MAXB = (MAXLINES * NB + NT - 1) / NT;
   constexpr int S = L / (NS * R);
-  constexpr int LS = lstride(L);
   const int total = nlines * NB;
   float2 v[MAXB][R];
   TwBase<R> wb[EARLY_TW && NS > 1 ? MAXB : 1];
@@ -301,12 +300,12 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int nlines, const flo
   __syncthreads();
 }
 
-template <int L, bool INV, int NT, int MAXLINES, bool EARLY_TW = false, int P = 0>
+template <int L, bool INV, int NT, int MAXLINES, bool EARLY_TW = false, int LS = lstride(L), int P = 0>
 __device__ __forceinline__ void fft_lines(float2* buf, int nlines, const float2* tw, unsigned tid = threadIdx.x) {
   if constexpr (P < RadixPlan<L>::npass) {
-    stockham_pass<L, RadixPlan<L>::radix(P), RadixPlan<L>::ns(P), INV, NT, MAXLINES, EARLY_TW>(buf, nlines, tw,
-                                                                                               tid);
-    fft_lines<L, INV, NT, MAXLINES, EARLY_TW, P + 1>(buf, nlines, tw, tid);
+    stockham_pass<L, RadixPlan<L>::radix(P), RadixPlan<L>::ns(P), INV, NT, MAXLINES, EARLY_TW, LS>(buf, nlines, tw,
+                                                                                                   tid);
+    fft_lines<L, INV, NT, MAXLINES, EARLY_TW, LS, P + 1>(buf, nlines, tw, tid);
   }
 }
 

@@ -100,8 +100,25 @@ constexpr bool kEarlyTwCol = (DCV_EARLY_TW & 2) != 0;
 #ifndef DCV_FULL_TILES
 #define DCV_FULL_TILES 0
 #endif
+// Line stride of the row tiles' LDS lines.  The spectrum gather and split
+// give consecutive threads the tile's RT rows at one frequency, so a wave's
+// 64 8-byte accesses fall on RT lines at once, 128/RT consecutive dwords on
+// each.  The 64 banks serve every one twice (the minimum) when the lines
+// start an odd multiple of 64/RT banks apart, i.e. stride = 32/RT (mod
+// 64/RT) in float2 units: lstride(L) is raised to the next such value for
+// 4 <= RT <= 32 (for RT <= 2 each line's accesses cover all banks anyway).
+// Measured with SQ_LDS_BANK_CONFLICT on MI355X: 4 lines at stride 1089 cost
+// three times the cycles of stride 1096.
+__host__ __device__ constexpr int row_lstride(int L, int RT) {
+  int s = lstride(L);
+  if (RT >= 4 && RT <= 32) {
+    const int m = 64 / RT;
+    while (s % m != m / 2) ++s;
+  }
+  return s;
+}
 __host__ __device__ constexpr int row_lds_elems(int L, int rt = 0) {
-  return ((rt > 0 ? rt : rt_for(L)) + 1) * lstride(L) + kTwLdsRow * L;
+  return ((rt > 0 ? rt : rt_for(L)) + 1) * row_lstride(L, rt > 0 ? rt : rt_for(L)) + kTwLdsRow * L;
 }
 // Lengths that also have row tiles of half the rows (rt_for(L) / 2), for
 // plans with too few tiles to fill the chip: those of at least 64 (a half
@@ -389,7 +406,7 @@ struct NoExtraLoads {
 template <int L, int RT, bool HALO = true, int NT = kNTR, class Extra = NoExtraLoads>
 __device__ __forceinline__ void gather_rows(const float4* __restrict__ sin, float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC, int rb, Extra extra = Extra()) {
-  constexpr int LS = lstride(L);
+  constexpr int LS = row_lstride(L, RT);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
   constexpr int NQ = (RT * NBC_MAX + NT - 1) / NT;
   constexpr int NH = (NBC_MAX + NT - 1) / NT;
@@ -465,7 +482,7 @@ __device__ __forceinline__ float row_x(const float2* buf, int l, int nr, int lj)
 template <int L, int RT, int NT = kNTR>
 __device__ __forceinline__ void split_store(float4* __restrict__ sout, const float2* buf, int M, int r0, int nr,
                                             int nh, int nb, int C, int logC, bool nt) {
-  constexpr int LS = lstride(L);
+  constexpr int LS = row_lstride(L, RT);
   constexpr int NBC_MAX = L / 2 + 16;   // >= nb * C
   constexpr int NQ = (RT * NBC_MAX + NT - 1) / NT;
 #pragma unroll
@@ -512,7 +529,7 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
                                              float4* __restrict__ sout, int M, int r0, int nh, int nb, int C,
                                              int logC, Pack pack, bool nt = false) {
   using PM = PixMap<L, NT>;
-  constexpr int LS = lstride(L);
+  constexpr int LS = row_lstride(L, RT);
   const unsigned tid = threadIdx.x;
   __builtin_assume(tid < (unsigned)NT);
   __syncthreads();
@@ -540,7 +557,7 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
     if (l <= nr && l >= 1) buf[(l - 1) * LS + lpad(j)] = wreg[k];
   }
   __syncthreads();
-  fft_lines<L, false, NT, RT, kEarlyTwRow>(buf, nr, tw);
+  fft_lines<L, false, NT, RT, kEarlyTwRow, LS>(buf, nr, tw);
   split_store<L, RT, NT>(sout, buf, M, r0, nr, nh, nb, C, logC, nt);
 }
 
@@ -553,7 +570,7 @@ __device__ __forceinline__ void row_prologue(float2* buf, float2 (&wreg)[KP], in
 template <int L, int RT>
 __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, int r0, float2* lds) {
   using PM = PixMap<L>;
-  constexpr int LS = lstride(L);
+  constexpr int LS = row_lstride(L, RT);
   constexpr int KP = ((RT + 1) * L + kNTR - 1) / kNTR;
   constexpr int NBC_MAX = L / 2 + 16;
   constexpr int NQ = (RT * NBC_MAX + kNTR - 1) / kNTR;
@@ -576,7 +593,7 @@ __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, i
     if (l >= 1 && l <= nr) yo[k] = yt[(unsigned)((r0 + l - 1) * L + j)];
   }
   __syncthreads();
-  fft_lines<L, true, kNTR, RT, kEarlyTwRow>(buf, nr, tw);
+  fft_lines<L, true, kNTR, RT, kEarlyTwRow, LS>(buf, nr, tw);
   // z-step on own row r = l - 1
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -606,7 +623,7 @@ __device__ __forceinline__ void row_inner(const RowArgs& a, const ImgMeta& mt, i
   }
   __syncthreads();
   const int npl = (nr + 1) >> 1;
-  fft_lines<L, false, kNTR, (RT + 1) / 2, kEarlyTwRow>(buf, npl, tw);
+  fft_lines<L, false, kNTR, (RT + 1) / 2, kEarlyTwRow, LS>(buf, npl, tw);
   float2* __restrict__ sout2 = reinterpret_cast<float2*>(a.spec_out + mt.sp);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
@@ -657,7 +674,7 @@ template <int L, int V, int RT, int NT = kNTR>
 __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& mt, int img, int r0, int nr,
                                               float2* lds) {
   using PM = PixMap<L, NT>;
-  constexpr int LS = lstride(L);
+  constexpr int LS = row_lstride(L, RT);
   constexpr int KP = ((RT + 1) * L + NT - 1) / NT;  // pixels per thread (own rows + 1 halo)
   const unsigned tid = threadIdx.x;
   __builtin_assume(tid < (unsigned)NT);
@@ -698,7 +715,7 @@ __device__ __forceinline__ void row_tile_rows(const RowArgs& a, const ImgMeta& m
                                  [&]() { twc.issue(tw_glob, tid); });
     tw = twc.commit(lds_tw, tw_glob, tid);
     __syncthreads();
-    fft_lines<L, true, NT, RT + 1, kEarlyTwRow>(buf, nr + 1, tw);
+    fft_lines<L, true, NT, RT + 1, kEarlyTwRow, LS>(buf, nr + 1, tw);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const int l = PM::row(k, tid), j = PM::col(k, tid);
