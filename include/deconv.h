@@ -110,7 +110,11 @@ typedef struct {
                            signature) */
   int32_t bgs_passes;   /* block-Gauss-Seidel passes of the x- and z-steps per
                            iteration, v and d frozen between them (Sec. III-B;
-                           "Proposed-AD" takes b of a (2b+1)^2 blur).  Default 1. */
+                           "Proposed-AD" takes b of a (2b+1)^2 blur), 1..64 for
+                           every image; 0: each image its own b = ksize/2 (at
+                           least 1), as Sec. III-B sets them (images with fewer
+                           passes than the batch's most skip the extra inner
+                           ones).  Default 1. */
   double adapt_t;       /* > 0: adapt mu every iteration with threshold t and
                            rescale d (eq. (varying_penalty), t = 3 in Sec.
                            III-B); 0 = fixed mu (default) */

@@ -210,6 +210,8 @@ struct deconv_plan_s {
   float4* specB = nullptr;
   float2* hh = nullptr;
   float* tab = nullptr;
+  int* npass = nullptr;       // per image: BGS passes per iteration
+  int max_pass = 1;
   float2* hsep = nullptr;     // separable blurs: 1-D spectra U, V (offsets of tab)
   int* sep = nullptr;         // per image: 1 = the column pass uses U V
   float2* tw = nullptr;
@@ -291,7 +293,7 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t off_meta, off_tiles, off_yt, off_d0, off_d1, off_v, off_specA, off_specB, off_hh, off_tab, off_tw,
       off_part, off_done, off_nonf, off_itd, off_stopbuf, off_res, off_mean, off_goff, off_hoff, off_hsum, off_mu,
-      off_dscale, off_small, off_hsep, off_sep;
+      off_dscale, off_small, off_npass, off_hsep, off_sep;
   size_t off_ck_yt, off_ck_v, off_ck_d, off_seg_u, off_seg_spec, off_adj_a, off_adj_b, off_adj_z, off_adj_y,
       off_adj_S, off_adj_lam, off_adj_vb, off_adj_db, off_adj_mean, off_tw64, off_adj_T;
   size_t total;
@@ -307,7 +309,7 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
     if (opt->schedule < 0 || opt->schedule > 3) return DECONV_ERR_INVALID_ARG;
     // the reverse pass replays every iteration: no early stopping with it
     if (opt->ckpt_every > 0 && (opt->tol_primal > 0 || opt->tol_dual > 0)) return DECONV_ERR_INVALID_ARG;
-    if (opt->bgs_passes < 1 || opt->bgs_passes > 64) return DECONV_ERR_INVALID_ARG;
+    if (opt->bgs_passes < 0 || opt->bgs_passes > 64) return DECONV_ERR_INVALID_ARG;
     if (!(opt->adapt_t >= 0.0) || opt->warm_iters < 0) return DECONV_ERR_INVALID_ARG;
     if (opt->warm_iters > 0 && !(opt->warm_tau > 0.f)) return DECONV_ERR_INVALID_ARG;
     // the reverse pass is derived for one pass, a fixed penalty and the plain
@@ -441,6 +443,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   lay.off_mu = take(sizeof(float) * B);
   lay.off_dscale = take(sizeof(float) * B);
   lay.off_small = take(sizeof(int) * B);
+  lay.off_npass = take(sizeof(int) * B);
   lay.off_hsep = take(sizeof(float2) * tab);
   lay.off_sep = take(sizeof(int) * B);
   const int ck = p->opt.ckpt_every;
@@ -747,6 +750,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   p->mu_cur = at<float>(w, lay.off_mu);
   p->dscale = at<float>(w, lay.off_dscale);
   p->d_small = at<int>(w, lay.off_small);
+  p->npass = at<int>(w, lay.off_npass);
   p->hsep = at<float2>(w, lay.off_hsep);
   p->sep = at<int>(w, lay.off_sep);
   if (p->opt.ckpt_every > 0) {
@@ -788,6 +792,14 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   }
   std::vector<float> tab(p->total_tab);
   std::vector<long long> goff(batch), hoff(batch);
+  // BGS passes per image: the option's count, or with 0 b passes for a
+  // (2b+1)^2 blur (Sec. III-B), at least one
+  std::vector<int> npass(batch);
+  p->max_pass = 1;
+  for (int b = 0; b < batch; ++b) {
+    npass[b] = p->opt.bgs_passes > 0 ? p->opt.bgs_passes : std::max(1, p->desc[b].ksize / 2);
+    p->max_pass = std::max(p->max_pass, npass[b]);
+  }
   for (int b = 0; b < batch; ++b) {
     const ImgMeta& m = p->meta[b];
     for (int k = 0; k < m.m; ++k) {
@@ -809,6 +821,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
       hipMemcpyAsync(p->tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(p->goff, goff.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(p->hoff, hoff.data(), sizeof(long long) * batch, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(p->npass, npass.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s) != hipSuccess ||
       // padded spectrum entries are never written by the passes: clear once
       hipMemsetAsync(p->specA, 0, sizeof(float4) * p->total_sp, s) != hipSuccess ||
       hipMemsetAsync(p->specB, 0, sizeof(float4) * p->total_sp, s) != hipSuccess ||
@@ -1339,10 +1352,18 @@ static deconv_status launch_iteration(deconv_plan_s* p, const uint8_t* mask, con
                                       int iters_since) {
   const bool adapt = p->opt.adapt_t > 0;
   const float* muk = mu_in_use(p, mu);
-  for (int q = 1; q < p->opt.bgs_passes; ++q) {
-    STCHK(launch_cols(p, col_args(p, muk)));
+  for (int q = 1; q < p->max_pass; ++q) {
+    // images with fewer passes than the plan's most skip the inner ones
+    // they do not have: their spectra stay as they are, so the passes they
+    // take are those of their own count
+    ColArgs ci = col_args(p, muk);
+    ci.npass = p->npass;
+    ci.pass_q = q;
+    STCHK(launch_cols(p, ci));
     RowArgs ra = row_args(p, mask, lam, muk);
     ra.mode = ROW_INNER;
+    ra.npass = p->npass;
+    ra.pass_q = q;
     STCHK(launch_rows(p, ra));
   }
   ColArgs ca = col_args(p, muk);

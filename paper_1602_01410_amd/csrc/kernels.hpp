@@ -225,6 +225,8 @@ struct RowArgs {
   double* partials;          // 3 doubles per row tile (when check)
   const int* done;           // per-image stop flags, nullable
   const float* dscale;       // ROW_STATE: per-image factor applied to d, nullable
+  const int* npass;          // per image: BGS passes; tiles of images with npass <= pass_q skip, nullable
+  int pass_q;
   float alpha;
   int mode, check, store_v, store_x, last;
   int nt_spec;               // non-temporal stores of spec_out
@@ -243,6 +245,8 @@ struct ColArgs {
   const float2* tw;
   float4* spec_store;        // (Y, X) per frequency for the backward, nullable
   const int* done;
+  const int* npass;          // as in RowArgs
+  int pass_q;
   int warm;                  // 1: quadratic warm-start solve (|H|^2 + warm_tau)
   float warm_tau;
   int nt_spec;               // non-temporal stores of spec_out
@@ -838,7 +842,7 @@ __global__ void __launch_bounds__(NT, NT == kNTR ? DCV_ROW_WAVES : DCV_ROW_WAVES
   static_assert(NT == kNTR || V != RV_GENERIC, "the generic variant runs kNTR threads");
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
-  if (t.x < 0 || (a.done && a.done[t.x])) return;
+  if (t.x < 0 || (a.done && a.done[t.x]) || (a.npass && a.pass_q >= a.npass[t.x])) return;
   row_tile<L, V, RT, NT>(a, t.x, t.y, lds);
 }
 
@@ -866,7 +870,7 @@ template <int V, int... Ls>
 __global__ void __launch_bounds__(kNTR, DCV_MULTI_ROW_WAVES) row_kernel_multi(RowArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
-  if (t.x < 0 || (a.done && a.done[t.x])) return;
+  if (t.x < 0 || (a.done && a.done[t.x]) || (a.npass && a.pass_q >= a.npass[t.x])) return;
   row_dispatch<V, Ls...>(a, a.meta[t.x].n, t.x, t.y, lds);
 }
 
@@ -1016,7 +1020,7 @@ template <int L, int NT = kNTC>
 __global__ void __launch_bounds__(NT) col_kernel(ColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
-  if (t.x < 0 || (a.done && a.done[t.x])) return;
+  if (t.x < 0 || (a.done && a.done[t.x]) || (a.npass && a.pass_q >= a.npass[t.x])) return;
   col_tile<L, NT>(a, t.x, t.y, lds);
 }
 
@@ -1033,7 +1037,7 @@ template <int... Ls>
 __global__ void __launch_bounds__(kNTC, DCV_MULTI_COL_WAVES) col_kernel_multi(ColArgs a) {
   extern __shared__ float2 lds[];
   const int4 t = a.tiles[blockIdx.x];
-  if (t.x < 0 || (a.done && a.done[t.x])) return;
+  if (t.x < 0 || (a.done && a.done[t.x]) || (a.npass && a.pass_q >= a.npass[t.x])) return;
   col_dispatch<Ls...>(a, a.meta[t.x].m, t.x, t.y, lds);
 }
 

@@ -51,7 +51,10 @@ def test_host_argument_checks():
            ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=0), 1),
            ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, tol_primal=1e-3), 1),
            ([dict(height=4096, width=64, ksize=5)], {}, 2),
-           ([dict(height=64, width=64, ksize=5)], dict(bgs_passes=0), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(bgs_passes=-1), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(bgs_passes=65), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(ckpt_every=5, max_iters=10, bgs_passes=0), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(separable_blur=2), 1),
            ([dict(height=64, width=64, ksize=5)], dict(adapt_t=-1.0), 1),
            ([dict(height=64, width=64, ksize=5)], dict(warm_iters=-1), 1),
            ([dict(height=64, width=64, ksize=5)], dict(warm_iters=10, warm_tau=0.0), 1),
@@ -68,6 +71,8 @@ def test_host_argument_checks():
         with pytest.raises(binding.DeconvError) as e:
             binding.workspace_size(images, **opts)
         assert e.value.code == code, (images, opts)
+    # per-image pass counts (0) are accepted
+    assert binding.workspace_size([dict(height=64, width=64, ksize=5)], bgs_passes=0) > 0
     # checkpoints grow the workspace
     a = binding.workspace_size([dict(height=64, width=64, ksize=5)])
     b = binding.workspace_size([dict(height=64, width=64, ksize=5)], ckpt_every=5, max_iters=20)

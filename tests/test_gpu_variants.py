@@ -106,7 +106,8 @@ def test_proposed_ad_full_configuration():
                            bsnr=40.0, lam=1e-3, mu=0.05, seed=51),
              _inpaint_96(seed=52)]
     iters = 30
-    # one plan shares bgs_passes: b of the larger kernel
+    # one pass count for the plan: b of the larger kernel (per-image counts
+    # are tested below)
     passes = max(p["K"] // 2 for p in probs)
     g = gpu_run(probs, iters, bgs_passes=passes, adapt_t=3.0, warm_iters=100, warm_tau=1e-3)
     for b, p in enumerate(probs):
@@ -139,3 +140,27 @@ def test_adaptive_penalty_continue_equals_longer_run():
     assert st[0]["mu"] == st_one[0]["mu"]
     assert_parity(x.cpu().numpy().astype(np.float64).reshape(p["M"], p["N"]), r["x"], what="x")
     assert torch.equal(x, x_one)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_proposed_ad_passes_per_image(use_graph):
+    """bgs_passes = 0: every image takes b passes for its (2b+1)^2 blur, the
+    rule of Sec. III-B, in one mixed batch (b = 1, 2, 4 and 6), with the
+    adaptive penalty (t = 3) and 100 warm-start steps; each image against the
+    oracle run with its own pass count."""
+    probs = [synth.problem(64, 64, 3, "rect", "gauss", sigma=0.8, bsnr=45.0, lam=1e-3, mu=0.05, seed=61),
+             synth.problem(72, 96, 5, "rect", "gauss", sigma=1.2, mask_kind=synth.MASK_DECIMATE, decim=2,
+                           bsnr=40.0, lam=1e-3, mu=0.05, seed=62),
+             synth.problem(96, 96, 9, "rect", "box", mask_kind=synth.MASK_EXPLICIT, missing=0.4, bsnr=45.0,
+                           lam=2e-3, mu=0.05, seed=63),
+             synth.problem(96, 128, 13, "rect", "motion", bsnr=40.0, lam=1e-3, mu=0.05, seed=64)]
+    iters = 24
+    g = gpu_run(probs, iters, bgs_passes=0, adapt_t=3.0, warm_iters=100, warm_tau=1e-3, check_every=8,
+                use_graph=use_graph)
+    for b, p in enumerate(probs):
+        passes = max(1, p["K"] // 2)
+        r = oracle_variant(p, iters, passes=passes, adapt_t=3.0, warm_iters=100, warm_tau=1e-3)
+        log("img%d: K=%d, %d passes, mu GPU %.6g oracle %.6g" % (b, p["K"], passes, g["stats"][b]["mu"], r["mu"]))
+        assert g["stats"][b]["mu"] == pytest.approx(r["mu"], rel=1e-6)
+        assert_parity(g["x"][b], r["x"], what="img%d x" % b)
+        assert_parity(g["yt"][b], r["yt"], what="img%d ytilde" % b)
