@@ -1386,7 +1386,7 @@ static deconv_status launch_iteration(deconv_plan_s* p, const uint8_t* mask, con
     // joint prox of each colour group: u (in d_out) -> v, d^{i+1}
     int ntile = 0;
     for (auto& m : p->meta) ntile = std::max(ntile, m.nrt);
-    hipLaunchKernelGGL(group_prox_kernel, dim3(ntile, p->batch / p->opt.channels), dim3(kNT), 0, p->ls,
+    hipLaunchKernelGGL(group_prox_kernel, dim3(ntile, p->batch / p->opt.channels), dim3(kNTProx), 0, p->ls,
                        p->d_meta, lam, muk, p->dbuf[p->cur_d], p->dbuf[1 - p->cur_d], p->v, p->partials,
                        resid ? 1 : 0, p->done);
     HIPCHK(hipGetLastError());

@@ -380,9 +380,14 @@ __global__ void __launch_bounds__(kNT) stopped_d_kernel(const ImgMeta* meta, con
 // and |v'-v|^2 of the tile go to its partials.  tau = lambda / mu of the
 // first channel.
 constexpr int kMaxChannels = 4;
-__global__ void __launch_bounds__(kNT) group_prox_kernel(const ImgMeta* meta, const float* lam, const float* mu,
-                                                         const float2* __restrict__ d_old, float2* d_new, float2* v,
-                                                         double* partials, int check, const int* done) {
+// 1024 threads per row tile: a colour image has few row tiles (288 rows: 36),
+// so each workgroup must keep many loads in flight (288 x 256 x 3 image: 31 us
+// per launch with 256 threads and one pixel per step, 9 us with 1024 threads
+// and every load of two pixels issued before their stores)
+constexpr int kNTProx = 1024;
+__global__ void __launch_bounds__(kNTProx) group_prox_kernel(const ImgMeta* meta, const float* lam, const float* mu,
+                                                            const float2* __restrict__ d_old, float2* d_new,
+                                                            float2* v, double* partials, int check, const int* done) {
   const int g0 = blockIdx.y * meta[0].nch;
   const ImgMeta mt = meta[g0];
   if (done && done[g0]) return;
@@ -394,34 +399,54 @@ __global__ void __launch_bounds__(kNT) group_prox_kernel(const ImgMeta* meta, co
   const long long plane = (long long)mt.m * mt.n;
   const int npx = nr * mt.n;
   float rd = 0.f, rv = 0.f;
-  for (int p = threadIdx.x; p < npx; p += kNT) {
-    const long long pix = mt.px + (long long)r0 * mt.n + p;
-    float2 u[kMaxChannels];
-    float n2 = 0.f;
+  // kProxPix pixels per thread and step, every load issued before the
+  // first store (the stores could alias the next loads as far as the
+  // compiler knows)
+  constexpr int kProxPix = 2;
+  for (int p0 = threadIdx.x; p0 < npx; p0 += kNTProx * kProxPix) {
+    float2 u[kProxPix][kMaxChannels], d0[kProxPix][kMaxChannels], v0[kProxPix][kMaxChannels];
 #pragma unroll
-    for (int c = 0; c < kMaxChannels; ++c)
-      if (c < mt.nch) {
-        u[c] = d_new[pix + c * plane];
-        n2 += u[c].x * u[c].x + u[c].y * u[c].y;
-      }
-    const float s = vsoft_scale(n2, tau, tau2);
+    for (int e = 0; e < kProxPix; ++e) {
+      const int p = p0 + e * kNTProx;
+      const long long pix = mt.px + (long long)r0 * mt.n + p;
 #pragma unroll
-    for (int c = 0; c < kMaxChannels; ++c)
-      if (c < mt.nch) {
-        const long long q = pix + c * plane;
-        const float2 vn = make_float2(s * u[c].x, s * u[c].y);
-        const float2 dn = make_float2(u[c].x - vn.x, u[c].y - vn.y);
-        if (check) {
-          const float2 d0 = d_old[q], v0 = v[q];
-          rd += (dn.x - d0.x) * (dn.x - d0.x) + (dn.y - d0.y) * (dn.y - d0.y);
-          rv += (vn.x - v0.x) * (vn.x - v0.x) + (vn.y - v0.y) * (vn.y - v0.y);
+      for (int c = 0; c < kMaxChannels; ++c)
+        if (p < npx && c < mt.nch) {
+          u[e][c] = d_new[pix + c * plane];
+          if (check) {
+            d0[e][c] = d_old[pix + c * plane];
+            v0[e][c] = v[pix + c * plane];
+          }
         }
-        v[q] = vn;
-        d_new[q] = dn;
-      }
+    }
+#pragma unroll
+    for (int e = 0; e < kProxPix; ++e) {
+      const int p = p0 + e * kNTProx;
+      if (p >= npx) continue;
+      const long long pix = mt.px + (long long)r0 * mt.n + p;
+      float n2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < kMaxChannels; ++c)
+        if (c < mt.nch) n2 += u[e][c].x * u[e][c].x + u[e][c].y * u[e][c].y;
+      const float s = vsoft_scale(n2, tau, tau2);
+#pragma unroll
+      for (int c = 0; c < kMaxChannels; ++c)
+        if (c < mt.nch) {
+          const long long q = pix + c * plane;
+          const float2 vn = make_float2(s * u[e][c].x, s * u[e][c].y);
+          const float2 dn = make_float2(u[e][c].x - vn.x, u[e][c].y - vn.y);
+          if (check) {
+            const float2 a = d0[e][c], b = v0[e][c];
+            rd += (dn.x - a.x) * (dn.x - a.x) + (dn.y - a.y) * (dn.y - a.y);
+            rv += (vn.x - b.x) * (vn.x - b.x) + (vn.y - b.y) * (vn.y - b.y);
+          }
+          v[q] = vn;
+          d_new[q] = dn;
+        }
+    }
   }
   if (check) {
-    __shared__ double red[3 * (kNT / 64)];
+    __shared__ double red[3 * (kNTProx / 64)];
     double a = rd, b = rv, z = 0.0;
     block_sum3(a, b, z, red);
     if (threadIdx.x == 0) {
