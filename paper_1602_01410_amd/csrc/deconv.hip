@@ -885,22 +885,24 @@ static uint64_t new_run_id() { return ++g_run_id; }
 static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out, bool pack = true) {
   hipStream_t s = p->stream;
   const int B = p->batch;
-  int maxk = 0, maxcol = 0, maxout = 0;
+  int maxk = 0, maxcol = 0, maxout = 0, maxm = 0;
   for (const ImgMeta& m : p->meta) {
     maxk = std::max(maxk, 2 * m.b + 1);
     maxcol = std::max(maxcol, m.nb * m.C);
     maxout = std::max(maxout, m.m + m.nb * m.C);
+    maxm = std::max(maxm, m.m);
   }
+  const int rowblk = (maxm + kBlurRows - 1) / kBlurRows;
   if (maxk <= kBlurMaxK) {
     if (full_out) {
       int maxn = 0;
       for (const ImgMeta& m : p->meta) maxn = std::max(maxn, m.n);
-      hipLaunchKernelGGL(blur_half_kernel, dim3((maxn + kBlurCols - 1) / kBlurCols, B), dim3(kNT), 0, s,
+      hipLaunchKernelGGL(blur_half_kernel, dim3((maxn + kBlurCols - 1) / kBlurCols, rowblk, B), dim3(kNT), 0, s,
                          p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, reinterpret_cast<float2*>(full_out));
       HIPCHK(hipGetLastError());
     }
     if (pack) {
-      hipLaunchKernelGGL(blur_half_kernel, dim3((maxcol + kBlurCols - 1) / kBlurCols, B), dim3(kNT), 0, s,
+      hipLaunchKernelGGL(blur_half_kernel, dim3((maxcol + kBlurCols - 1) / kBlurCols, rowblk, B), dim3(kNT), 0, s,
                          p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, nullptr);
       HIPCHK(hipGetLastError());
     }

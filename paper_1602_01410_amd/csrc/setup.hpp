@@ -84,23 +84,26 @@ __global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ 
 // centred at the origin (as embed_psf_kernel places it),
 //   H(ky, kx) = sum_p w_m^(ky p) T(p, kx),  T(p, kx) = sum_q h(p, q) w_n^(kx q),
 // p, q = -b..b, w_L = exp(-2 pi i / L) read from the twiddle tables (phase
-// indices reduced exactly).  One workgroup per image and block of kBlurCols
-// spectrum columns: T of its columns in LDS, then every row ky; written in
-// the tiled half layout the column pass reads (zero past nh), or, with
-// full, as the whole m' x n' spectrum (row-major at the image's pixel
-// offset); H(0, 0) into hsum.  Kernels up to kBlurMaxK taps a side; FP32
-// sums of K terms.
+// indices reduced exactly).  One workgroup per image, block of kBlurCols
+// spectrum columns and block of kBlurRows rows: T of its columns in LDS,
+// then its rows; written in the tiled half layout the column pass reads
+// (zero past nh), or, with full, as the whole m' x n' spectrum (row-major at
+// the image's pixel offset); H(0, 0) into hsum.  Kernels up to kBlurMaxK
+// taps a side; FP32 sums of K terms.
 constexpr int kBlurCols = 32;
+constexpr int kBlurRows = 64;
 constexpr int kBlurMaxK = 65;
 __global__ void __launch_bounds__(kNT) blur_half_kernel(const ImgMeta* meta, const float* __restrict__ h,
                                                        const long long* hoff, const float2* __restrict__ tw,
                                                        float2* hh, float2* hsum, float2* full) {
-  const int img = blockIdx.y;
+  const int img = blockIdx.z;
   const ImgMeta mt = meta[img];
   const int ncol = full ? mt.n : mt.nb * mt.C;
   const int nval = full ? mt.n : mt.nh;   // columns with values (zero past them)
   const int kx0 = blockIdx.x * kBlurCols;
-  if (kx0 >= ncol) return;
+  const int ky0 = blockIdx.y * kBlurRows;
+  if (kx0 >= ncol || ky0 >= mt.m) return;
+  const int nrow = min(kBlurRows, mt.m - ky0);
   const int b = mt.b, K = 2 * b + 1;
   const float* __restrict__ hk = h + hoff[img];
   const float2* __restrict__ twn = tw + mt.twr;
@@ -124,8 +127,8 @@ __global__ void __launch_bounds__(kNT) blur_half_kernel(const ImgMeta* meta, con
     T[t] = make_float2(re, im);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < mt.m * kBlurCols; t += kNT) {
-    const int ky = t / kBlurCols, c = t % kBlurCols, kx = kx0 + c;
+  for (int t = threadIdx.x; t < nrow * kBlurCols; t += kNT) {
+    const int ky = ky0 + t / kBlurCols, c = t % kBlurCols, kx = kx0 + c;
     if (kx >= ncol) continue;
     float re = 0.f, im = 0.f;
     if (kx < nval) {
@@ -248,7 +251,7 @@ __global__ void pack_half_kernel(const ImgMeta* meta, const float2* __restrict__
           kx < mt.nh ? g[(long long)ky * mt.n + kx] : make_float2(0.f, 0.f);
 }
 
-constexpr int kMeanBlocks = 64;
+constexpr int kMeanBlocks = 256;   // blocks of rows per image (partial sums of the observed mean)
 
 // per image and block of rows: FP64 sum and count of the observed pixels
 __global__ void __launch_bounds__(kNT) observed_sum_kernel(const ImgMeta* meta, const float* __restrict__ y,
