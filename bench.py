@@ -393,7 +393,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
