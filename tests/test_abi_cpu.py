@@ -104,3 +104,18 @@ def test_binding_struct_layout_matches_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f in cls._fields_:
             assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
+
+
+def test_option_defaults_match_header():
+    """deconv_options_default fills the defaults the header documents."""
+    if not os.path.exists(LIB):
+        pytest.skip("libdeconv.so not built")
+    from paper_1602_01410_amd import binding
+    o = binding.default_options()
+    assert o.alpha == 2.0
+    assert (o.check_every, o.use_graph, o.batched, o.ckpt_every, o.profile, o.schedule) == (0, 1, 1, 0, 0, 0)
+    assert (o.tol_primal, o.tol_dual, o.adapt_t) == (0.0, 0.0, 0.0)
+    assert (o.bgs_passes, o.warm_iters, o.channels, o.spectra_hint) == (1, 0, 1, 0)
+    assert abs(o.warm_tau - 1e-3) < 1e-9
+    assert (o.row_tiles, o.row_threads, o.col_threads, o.small_images, o.separable_blur) == (0, 0, 0, 0, 1)
+    assert not o.tune_cache
