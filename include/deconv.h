@@ -146,15 +146,18 @@ typedef struct {
                            row_tiles, 512 or 1024.  Default 0. */
   int32_t col_threads;  /* threads per column tile of length >= 512: 0 = as
                            row_tiles, 256 or 512.  Default 0. */
-  int32_t small_images; /* 1: plans whose images are all square with a side
+  int32_t small_images; /* Plans whose images are all square with a side
                            of 32, 48, 64, 72 or 96 and that use one BGS pass,
                            a fixed penalty, grey images and no checkpoints
-                           run every iteration of a check period in one
+                           can run every iteration of a check period in one
                            workgroup per image, the image held in LDS (one
                            launch per check period instead of two per
-                           iteration); 0: never (default: on MI355X the
-                           two-pass kernels are as fast for one 72^2 image
-                           and faster for batches of small images). */
+                           iteration).  2 (default): such plans whose sides
+                           are all at most 72 take it (on MI355X it is 1.1x
+                           to 2.4x as fast there; one 96^2 image is faster
+                           on the two-pass kernels); 1: every such plan
+                           takes it; 0: never.  The iterates agree with the
+                           two-pass kernels' to within rounding. */
   int32_t separable_blur; /* 1 (default): the column pass of an image whose
                            blur kernel is the outer product of two 1-D kernels
                            (to within 1e-6 of its largest tap: box and

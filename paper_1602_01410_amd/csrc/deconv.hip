@@ -326,7 +326,7 @@ static deconv_status validate(int32_t batch, const deconv_image_desc* desc, cons
       return DECONV_ERR_INVALID_ARG;
     if (opt->col_threads != 0 && opt->col_threads != kNTC && opt->col_threads != kNTCWide)
       return DECONV_ERR_INVALID_ARG;
-    if (opt->small_images < 0 || opt->small_images > 1) return DECONV_ERR_INVALID_ARG;
+    if (opt->small_images < 0 || opt->small_images > 2) return DECONV_ERR_INVALID_ARG;
     if (opt->separable_blur < 0 || opt->separable_blur > 1) return DECONV_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
       const deconv_image_desc& f = desc[b - b % opt->channels];
@@ -659,7 +659,7 @@ extern "C" deconv_status deconv_options_default(deconv_options* opt) {
   opt->row_tiles = 0;
   opt->row_threads = 0;
   opt->col_threads = 0;
-  opt->small_images = 0;
+  opt->small_images = 2;
   opt->separable_blur = 1;
   return DECONV_OK;
 }
@@ -830,12 +830,18 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
       hipMemsetAsync(p->sep, 0, sizeof(int) * batch, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(DECONV_ERR_HIP);
-  // the whole-image-in-LDS path (asked for with opt.small_images = 1) takes
-  // the plan when every image has one and the options need nothing it lacks
-  // (one pass, fixed penalty, grey images, no checkpoints)
-  p->small = p->opt.small_images == 1 && p->opt.bgs_passes == 1 && !(p->opt.adapt_t > 0) &&
+  // the whole-image-in-LDS path takes the plan when every image has one and
+  // the options need nothing it lacks (one pass, fixed penalty, grey images,
+  // no checkpoints): always with opt.small_images = 1, and with 2 (the
+  // default) when no side exceeds kSmallAutoSide (measured on MI355X against
+  // the two-pass kernels: one image of side 32 / 48 / 64 / 72 2.4 / 1.8 /
+  // 1.3 / 1.1x as fast, 64 images of 72^2 1.4x, 256 of 64^2 1.9x; one 96^2
+  // image 0.6x)
+  p->small = p->opt.small_images != 0 && p->opt.bgs_passes == 1 && !(p->opt.adapt_t > 0) &&
              p->opt.channels == 1 && p->opt.ckpt_every == 0;
-  for (auto& d : p->desc) p->small = p->small && has_small_path(d.height, d.width);
+  for (auto& d : p->desc)
+    p->small = p->small && has_small_path(d.height, d.width) &&
+               (p->opt.small_images == 1 || std::max(d.height, d.width) <= kSmallAutoSide);
   if (p->small) {
     std::vector<int> order(batch);
     for (int b = 0; b < batch; ++b) order[b] = b;

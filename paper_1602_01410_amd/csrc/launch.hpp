@@ -120,6 +120,9 @@ hipError_t launch_col(int L, int grid, size_t lds, hipStream_t s, ColArgs a, hip
 // whole-image-in-LDS path (small.hpp): square images of a few sides
 struct SmallArgs;
 bool has_small_path(int M, int N);
+// largest side that the default option (small_images = 2) sends to the
+// whole-image-in-LDS path
+constexpr int kSmallAutoSide = 72;
 hipError_t launch_small(int M, int N, int grid, hipStream_t s, SmallArgs a, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 hipError_t launch_bwd_row(int L, int grid, size_t lds, hipStream_t s, BwdRowArgs a, hipEvent_t e0 = nullptr,

@@ -1,4 +1,6 @@
 // Instantiations and launcher of the whole-image-in-LDS path (small.hpp).
+#include <algorithm>
+
 #include "launch.hpp"
 #include "small.hpp"
 
@@ -35,7 +37,10 @@ hipError_t launch_small(int M, int N, int grid, hipStream_t s, SmallArgs a, hipE
   if (M <= 0) {
     // images of several sides: one launch, LDS for the largest (-M)
     static bool attr = false;
-    const size_t lds = SmallShape<96, 96>::lds_bytes;
+    size_t lds = 0;
+#define DCV_CASE(n) lds = std::max(lds, SmallShape<n, n>::lds_bytes);
+    DCV_FOR_EACH_SMALL_SIDE(DCV_CASE)
+#undef DCV_CASE
     const auto k = small_kernel_multi<DCV_SMALL_SIDE_ARGS>;
     if (!attr) {
       const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),

@@ -100,8 +100,11 @@ struct SmallShape {
   static constexpr int KP = (NPX + kNTS - 1) / kNTS;                // pixels per thread
   static constexpr int NHALF = M * (N / 2 + 1);                      // half-spectrum frequencies
   static constexpr int KF = (NHALF + kNTS - 1) / kNTS;               // frequencies per thread
-  // C, W, then the twiddle tables of both lengths
-  static constexpr size_t lds_bytes = ((size_t)2 * M * LSN + M + N) * sizeof(float2);
+  // C, W, the twiddle tables of both lengths, then (where it fits) the
+  // per-frequency constants (H, |D|^2) of the x-step as float4
+  static constexpr size_t base_bytes = ((size_t)2 * M * LSN + M + N) * sizeof(float2);
+  static constexpr bool kConstLds = base_bytes + (size_t)NHALF * sizeof(float4) <= 160 * 1024;
+  static constexpr size_t lds_bytes = base_bytes + (kConstLds ? (size_t)NHALF * sizeof(float4) : 0);
 };
 
 template <int M, int N>
@@ -138,6 +141,7 @@ template <int M, int N>
 __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2* lds) {
   using SS = SmallShape<M, N>;
   constexpr int LSN = SS::LSN, KP = SS::KP, KF = SS::KF, NH = N / 2 + 1;
+  static_assert(KP <= 32 && KF <= 32, "per-thread flags are kept in one word");
   float2* C = lds;                 // the complex image / spectrum
   float2* W = lds + M * LSN;       // w = v - d, kept here between iterations
   const ImgMeta mt = a.meta[img];
@@ -156,22 +160,65 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
   float2* twc = twr + N;
   for (int t = (int)threadIdx.x; t < N; t += kNTS) twr[t] = a.tw[mt.twr + t];
   for (int t = (int)threadIdx.x; t < M; t += kNTS) twc[t] = a.tw[mt.twc + t];
+  // per frequency f of the half spectrum (ky = f / NH, kx = f mod NH): H and
+  // |D_h|^2 + |D_v|^2, in LDS where they fit (else read per iteration)
+  float4* HT = reinterpret_cast<float4*>(twc + M);
+  if constexpr (SS::kConstLds) {
+    for (int f = (int)threadIdx.x; f < SS::NHALF; f += kNTS) {
+      const int ky = f / NH, kx = f - ky * NH;
+      const float2 H = hh[((kx >> mt.logC) * M + ky) * mt.C + (kx & (mt.C - 1))];
+      HT[f] = make_float4(H.x, H.y, tab[ky] + tab[M + kx], 0.f);
+    }
+  }
 
   // registers: ytilde and d of the thread's pixels p = tid + k kNTS, which
-  // of them are observed; w = v - d lives in W
+  // of them are observed; w = v - d lives in W.  Each pixel's LDS offset
+  // i LSN + lpad(j) and the flags that give its neighbours' offsets (the
+  // last / first column and row, and where lpad steps by 2) are computed
+  // once, so that the loop does no division.
   float yv[KP];
   float2 dv[KP];
-  unsigned obs = 0;
+  int poff[KP];
+  unsigned obs = 0, jlast = 0, jfirst = 0, ilast = 0, ifirst = 0, padr = 0, padl = 0;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int p = (int)threadIdx.x + k * kNTS;
+    poff[k] = 0;
     if (p < SS::NPX) {
       const int i = p / N, j = p - i * N;
+      poff[k] = i * LSN + lpad(j);
       yv[k] = yt[p];
       dv[k] = dg[p];
       const float2 v0 = vg[p];
-      W[i * LSN + lpad(j)] = make_float2(v0.x - dv[k].x, v0.y - dv[k].y);
+      W[poff[k]] = make_float2(v0.x - dv[k].x, v0.y - dv[k].y);
       if (observed(mt, a.mask, i, j)) obs |= 1u << k;
+      if (j == N - 1) jlast |= 1u << k;
+      if (j == 0) jfirst |= 1u << k;
+      if (i == M - 1) ilast |= 1u << k;
+      if (i == 0) ifirst |= 1u << k;
+      if ((j & 15) == 15) padr |= 1u << k;   // lpad(j + 1) = lpad(j) + 2
+      if ((j & 15) == 0) padl |= 1u << k;    // lpad(j - 1) = lpad(j) - 2 (j > 0)
+    }
+  }
+  // the thread's frequencies f = tid + k kNTS of the half spectrum (kx <=
+  // N/2; on the columns kx = 0 and kx = N/2 only ky <= M/2, whose partner
+  // (-ky, kx) lies in the same column): offsets of (ky, kx) and (-ky, -kx),
+  // which of them take part and which are their own partner
+  int foff[KF], fmoff[KF];
+  unsigned fact = 0, fself = 0;
+#pragma unroll
+  for (int k = 0; k < KF; ++k) {
+    const int f = (int)threadIdx.x + k * kNTS;
+    foff[k] = 0;
+    fmoff[k] = 0;
+    if (f < SS::NHALF) {
+      const int ky = f / NH, kx = f - ky * NH;
+      const bool edge = kx == 0 || 2 * kx == N;
+      const int ny = ky == 0 ? 0 : M - ky, nx = kx == 0 ? 0 : N - kx;
+      foff[k] = ky * LSN + lpad(kx);
+      fmoff[k] = ny * LSN + lpad(nx);
+      if (!edge || 2 * ky <= M) fact |= 1u << k;
+      if (ny == ky && nx == kx) fself |= 1u << k;
     }
   }
   const float scale = 1.0f / ((float)M * (float)N);
@@ -180,54 +227,61 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
   for (int it = 0; it < a.iters; ++it) {
     const bool last = it + 1 == a.iters;
     const bool chk = last && a.check;
-    // the thread index made opaque per iteration: pixel and frequency
-    // addresses are recomputed (cheap) rather than kept in registers across
-    // the loop
+    // the offsets and the thread index made opaque per iteration: addresses
+    // derived from them are formed where they are used rather than kept in
+    // registers across the loop
     unsigned tid = threadIdx.x;
     __asm__ volatile("" : "+v"(tid));
+#pragma unroll
+    for (int k = 0; k < KP; ++k) __asm__ volatile("" : "+v"(poff[k]));
+#pragma unroll
+    for (int k = 0; k < KF; ++k) __asm__ volatile("" : "+v"(foff[k]), "+v"(fmoff[k]));
     __syncthreads();   // W written (before the loop or by the last epilogue)
     // C <- ytilde + i mu D^T w: g = w_h[i, j-1] - w_h[i, j] + w_v[i-1, j] - w_v[i, j]
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const int p = (int)tid + k * kNTS;
       if (p < SS::NPX) {
-        const int i = p / N, j = p - i * N;
-        const float2 w = W[i * LSN + lpad(j)];
-        const float wl = W[i * LSN + lpad(j == 0 ? N - 1 : j - 1)].x;
-        const float wu = W[(i == 0 ? M - 1 : i - 1) * LSN + lpad(j)].y;
-        C[i * LSN + lpad(j)] = make_float2(yv[k], mu * (wl - w.x + wu - w.y));
+        const int o = poff[k];
+        const int ol = (jfirst >> k) & 1u ? o + lpad(N - 1) : o - 1 - (int)((padl >> k) & 1u);
+        const int ou = (ifirst >> k) & 1u ? o + (M - 1) * LSN : o - LSN;
+        const float2 w = W[o];
+        const float wl = W[ol].x;
+        const float wu = W[ou].y;
+        C[o] = make_float2(yv[k], mu * (wl - w.x + wu - w.y));
       }
       if (k % 2 == 1) small_group_fence();
     }
     __syncthreads();
     fft_lines<N, false, kNTS, M>(C, M, twr, tid);
     fft_cols_lds<M, N, false, kNTS, LSN>(C, twc, tid);
-    // x-step per frequency pair (C holds F(ytilde) + i F(mu g)).  The
-    // thread's frequencies f = tid + k kNTS of the half spectrum (kx <= N/2;
-    // on the columns kx = 0 and kx = N/2 only ky <= M/2, whose partner
-    // (-ky, kx) lies in the same column): each slot is read and written by
-    // one thread.
+    // x-step per frequency pair (C holds F(ytilde) + i F(mu g)); each slot
+    // is read and written by one thread
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
       const int f = (int)tid + k * kNTS;
-      if (f < SS::NHALF) {
-        const int ky = f / NH, kx = f - ky * NH;
-        const bool edge = kx == 0 || 2 * kx == N;
-        if (!edge || 2 * ky <= M) {
-          const float2 H = hh[((kx >> mt.logC) * M + ky) * mt.C + (kx & (mt.C - 1))];
-          const float ds = tab[ky] + tab[M + kx];
-          const int ny = ky == 0 ? 0 : M - ky, nx = kx == 0 ? 0 : N - kx;
-          const float2 c = C[ky * LSN + lpad(kx)];
-          const float2 cm = C[ny * LSN + lpad(nx)];
-          // Y = (c + conj cm) / 2, G = (c - conj cm) / 2i
-          const float2 Y = make_float2(0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y));
-          const float2 G = make_float2(0.5f * (c.y + cm.y), 0.5f * (cm.x - c.x));
-          const float inv = scale * frcp(H.x * H.x + H.y * H.y + mu * ds);
-          const float2 X = make_float2((H.x * Y.x + H.y * Y.y + G.x) * inv, (H.x * Y.y - H.y * Y.x + G.y) * inv);
-          const float2 Q = cmul(H, X);
-          C[ky * LSN + lpad(kx)] = make_float2(X.x - Q.y, X.y + Q.x);
-          if (ny != ky || nx != kx) C[ny * LSN + lpad(nx)] = make_float2(X.x + Q.y, Q.x - X.y);
+      if ((fact >> k) & 1u) {
+        float2 H;
+        float ds;
+        if constexpr (SS::kConstLds) {
+          const float4 t = HT[f];
+          H = make_float2(t.x, t.y);
+          ds = t.z;
+        } else {
+          const int ky = f / NH, kx = f - ky * NH;
+          H = hh[((kx >> mt.logC) * M + ky) * mt.C + (kx & (mt.C - 1))];
+          ds = tab[ky] + tab[M + kx];
         }
+        const float2 c = C[foff[k]];
+        const float2 cm = C[fmoff[k]];
+        // Y = (c + conj cm) / 2, G = (c - conj cm) / 2i
+        const float2 Y = make_float2(0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y));
+        const float2 G = make_float2(0.5f * (c.y + cm.y), 0.5f * (cm.x - c.x));
+        const float inv = scale * frcp(H.x * H.x + H.y * H.y + mu * ds);
+        const float2 X = make_float2((H.x * Y.x + H.y * Y.y + G.x) * inv, (H.x * Y.y - H.y * Y.x + G.y) * inv);
+        const float2 Q = cmul(H, X);
+        C[foff[k]] = make_float2(X.x - Q.y, X.y + Q.x);
+        if (!((fself >> k) & 1u)) C[fmoff[k]] = make_float2(X.x + Q.y, Q.x - X.y);
       }
       small_group_fence();
     }
@@ -240,11 +294,13 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
     for (int k = 0; k < KP; ++k) {
       const int p = (int)tid + k * kNTS;
       if (p < SS::NPX) {
-        const int i = p / N, j = p - i * N;
-        const float2 c = C[i * LSN + lpad(j)];
+        const int o = poff[k];
+        const int orr = (jlast >> k) & 1u ? o - lpad(N - 1) : o + 1 + (int)((padr >> k) & 1u);
+        const int od = (ilast >> k) & 1u ? o - (M - 1) * LSN : o + LSN;
+        const float2 c = C[o];
         const float x = c.x;
-        const float xr = C[i * LSN + lpad(j + 1 == N ? 0 : j + 1)].x;
-        const float xd = C[(i + 1 == M ? 0 : i + 1) * LSN + lpad(j)].x;
+        const float xr = C[orr].x;
+        const float xd = C[od].x;
         if (!((obs >> k) & 1u)) {
           const float yn = yv[k] + alpha * (c.y - yv[k]);
           if (chk) rz += (yn - yv[k]) * (yn - yv[k]);
@@ -254,7 +310,7 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
         const float sc = vsoft_scale(uh * uh + uv * uv, tau, tau2);
         const float vh = sc * uh, vw = sc * uv;
         const float dh = uh - vh, dw = uv - vw;
-        float2* wp = W + i * LSN + lpad(j);
+        float2* wp = W + o;
         if (chk) {
           const float2 w0 = *wp;   // v = w + d of the previous iteration
           const float v0h = w0.x + dv[k].x, v0v = w0.y + dv[k].y;

@@ -65,7 +65,7 @@ def test_host_argument_checks():
            ([dict(height=64, width=64, ksize=5)], dict(row_tiles=3), 1),
            ([dict(height=64, width=64, ksize=5)], dict(row_threads=256), 1),
            ([dict(height=64, width=64, ksize=5)], dict(col_threads=1024), 1),
-           ([dict(height=64, width=64, ksize=5)], dict(small_images=2), 1),
+           ([dict(height=64, width=64, ksize=5)], dict(small_images=3), 1),
            ([], {}, 1)]                                            # empty batch
     for images, opts, code in bad:
         with pytest.raises(binding.DeconvError) as e:
@@ -117,5 +117,5 @@ def test_option_defaults_match_header():
     assert (o.tol_primal, o.tol_dual, o.adapt_t) == (0.0, 0.0, 0.0)
     assert (o.bgs_passes, o.warm_iters, o.channels, o.spectra_hint) == (1, 0, 1, 0)
     assert abs(o.warm_tau - 1e-3) < 1e-9
-    assert (o.row_tiles, o.row_threads, o.col_threads, o.small_images, o.separable_blur) == (0, 0, 0, 0, 1)
+    assert (o.row_tiles, o.row_threads, o.col_threads, o.small_images, o.separable_blur) == (0, 0, 0, 2, 1)
     assert not o.tune_cache

@@ -129,11 +129,14 @@ def test_one_iteration_full_state(torch_cuda):
         assert np.linalg.norm(g["d"][b] - dref) <= 1e-5 * scale
 
 
-def test_plain_72_config_200_iterations(torch_cuda):
+@pytest.mark.parametrize("small_images", [0, 2])
+def test_plain_72_config_200_iterations(torch_cuda, small_images):
     """72x72 domain, 9x9 box, observed 64x64, BSNR 50, lambda 1e-3, mu 0.05,
-    200 iterations: relative L2 <= 1e-4, max abs <= 1e-3 of the range."""
+    200 iterations: relative L2 <= 1e-4, max abs <= 1e-3 of the range, on the
+    two-pass kernels and on the default path (the image in LDS)."""
     p = synth.config_plain_72()
-    g = gpu_run([p], p["iters"])
+    g = gpu_run([p], p["iters"], small_images=small_images)
+    assert g["plan"].tiles()[3] == (1 if small_images else 0)
     r = oracle_run(p, p["iters"])
     assert_parity(g["x"][0], r["x"], what="x")
     assert_parity(g["yt"][0], r["yt"], what="ytilde")

@@ -1,6 +1,6 @@
-"""The whole-image-in-LDS path (option small_images = 1; square images of side
-32, 48, 64, 72 or 96: one workgroup per image runs a whole check period with
-the image in LDS) against the FP64 oracle, element by element: the 72^2 workload (config 1)
+"""The whole-image-in-LDS path (square images of side 32, 48, 64, 72 or 96:
+one workgroup per image runs a whole check period with the image in LDS; by
+default for sides up to 72, with option small_images = 1 for all) against the FP64 oracle, element by element: the 72^2 workload (config 1)
 at its full 200 iterations, a batch of every side and mask kind, runs
 without checks (launches of 50 iterations), early stopping, continue, and
 NaN reporting.  The plan reports the path it takes."""
@@ -55,12 +55,33 @@ def test_every_side_and_mask(check_every):
 def test_same_iterates_as_the_two_pass_kernels():
     probs = _batch()[:4]
     a = gpu_run(probs, 40, check_every=10, small_images=1)
-    b = gpu_run(probs, 40, check_every=10)
+    b = gpu_run(probs, 40, check_every=10, small_images=0)
     assert a["plan"].tiles()[3] == 1 and b["plan"].tiles()[3] == 0
     for k in range(len(probs)):
         r = oracle_run(probs[k], 40)
         assert_parity(a["x"][k], r["x"], what="small path img%d" % k)
         assert_parity(b["x"][k], r["x"], what="two-pass img%d" % k)
+
+
+def test_default_routing():
+    """With the default option the plan takes the path for images of side at
+    most 72 only, and only with the options the path supports."""
+    from paper_1602_01410_amd import binding
+    def path(sides, **kw):
+        pl = binding.Plan([dict(height=s, width=s, ksize=5) for s in sides], **kw)
+        try:
+            return pl.tiles()[3]
+        finally:
+            pl.close()
+    assert path([32, 48, 64, 72]) == 1
+    assert path([72] * 8) == 1
+    assert path([96]) == 0 and path([64, 96]) == 0
+    assert path([96], small_images=1) == 1
+    assert path([64], small_images=0) == 0
+    assert path([64], bgs_passes=2) == 0 and path([64], adapt_t=3.0) == 0
+    pl = binding.Plan([dict(height=64, width=48, ksize=5)])
+    assert pl.tiles()[3] == 0
+    pl.close()
 
 
 def test_early_stop_and_continue():
