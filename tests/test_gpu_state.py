@@ -15,6 +15,8 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "boundary": dict(M=96, N=128, K=7, mask_kind=synth.MASK_BOUNDARY),
     "missing": dict(M=72, N=96, K=5, mask_kind=synth.MASK_EXPLICIT),
+    # square and small: the plan runs the whole-image-in-LDS kernel
+    "small": dict(M=64, N=64, K=5, mask_kind=synth.MASK_DECIMATE),
 }
 
 
@@ -42,6 +44,7 @@ def test_import_oracle_state_then_continue(case):
     v0, d0 = _interleave(st["vh"], st["vv"]), _interleave(st["dh"], st["dv"])
     x_ref, _, _, _ = oracle.admm_iterate(st, h64, m, lam, mu, n1)
     plan = binding.Plan([desc(p)])
+    assert plan.tiles()[3] == (1 if case == "small" else 0)
     y, mask, h, lamt, mut = device_inputs([p])
     dev = y.device
     imp_mask = mask if p["mask_kind"] == synth.MASK_EXPLICIT else None
@@ -55,10 +58,11 @@ def test_import_oracle_state_then_continue(case):
     assert_parity(yt.cpu().numpy().astype(np.float64).reshape(sh), st["yt"], what="ytilde")
 
 
-def test_export_import_roundtrip_bitwise():
+@pytest.mark.parametrize("case", ["missing", "small"])
+def test_export_import_roundtrip_bitwise(case):
     import torch
     from paper_1602_01410_amd import binding
-    p = _problem(CASES["missing"])
+    p = _problem(CASES[case])
     log("export/import round trip: %dx%d, 12 + 9 iterations" % (p["M"], p["N"]))
     y, mask, h, lam, mu = device_inputs([p])
     a = binding.Plan([desc(p)], check_every=5)
@@ -66,6 +70,7 @@ def test_export_import_roundtrip_bitwise():
     a.run(y, mask, h, lam, mu, 12, x_out=xa)
     yt, v, d = a.state_export(y.device)
     b = binding.Plan([desc(p)], check_every=5)
+    assert a.tiles()[3] == (1 if case == "small" else 0)
     b.state_import(mask, h, yt.clone(), v.clone(), d.clone())
     xb = torch.empty_like(y)
     b.cont(lam, mu, 9, xb)

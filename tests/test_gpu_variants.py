@@ -87,12 +87,13 @@ def test_adaptive_penalty_graph_and_state():
     assert_parity(g["d"][0].reshape(d_ref.shape), d_ref, rel=1e-3, absfrac=1e-2, what="d")
 
 
-@pytest.mark.parametrize("iters", [1, 40])
-def test_warm_start(iters):
+@pytest.mark.parametrize("iters,small", [(1, 0), (40, 0), (40, 1)])
+def test_warm_start(iters, small):
     """100 warm-start steps with tau = 1e-3 on an inpainting problem, then
-    `iters` iterations."""
+    `iters` iterations (on the whole-image-in-LDS kernel with small = 1)."""
     p = _inpaint_96()
-    g = gpu_run([p], iters, warm_iters=100, warm_tau=1e-3)
+    g = gpu_run([p], iters, warm_iters=100, warm_tau=1e-3, small_images=small)
+    assert g["plan"].tiles()[3] == small
     r = oracle_variant(p, iters, warm_iters=100, warm_tau=1e-3)
     assert_parity(g["x"][0], r["x"], what="x")
     assert_parity(g["yt"][0], r["yt"], what="ytilde")
