@@ -265,6 +265,7 @@ struct deconv_plan_s {
 
   const uint8_t* mask = nullptr;  // explicit masks of the last run (caller-owned)
   int cur_d = 0;        // index of the d buffer holding the current state
+  int max_height = 0;   // tallest image of the batch
   bool have_state = false;
   bool wide_col = false;     // column tiles of kNTCWide threads (few tiles)
   bool wide_row = false;     // half-height row tiles of kNTRWide threads (few tiles)
@@ -708,6 +709,7 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   if (!p) return DECONV_ERR_OOM;
   p->batch = batch;
   p->desc.assign(desc, desc + batch);
+  for (auto& d : p->desc) p->max_height = std::max(p->max_height, (int)d.height);
   if (opt) p->opt = *opt; else deconv_options_default(&p->opt);
   p->stream = static_cast<hipStream_t>(stream);
   p->ls = p->stream;
@@ -1656,14 +1658,16 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
                      p->mean);
   HIPCHK(hipGetLastError());
   p->cur_d = 0;
-  hipLaunchKernelGGL(init_state_kernel, dim3(256, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask, p->mean,
-                     kMeanBlocks, p->yt, p->v, p->dbuf[0]);
+  hipLaunchKernelGGL(init_state_kernel, dim3(p->max_height, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask,
+                     p->mean, kMeanBlocks, p->yt, p->v, p->dbuf[0]);
   HIPCHK(hipGetLastError());
   if (p->opt.adapt_t > 0) {
     HIPCHK(hipMemcpyAsync(p->mu_cur, mu, sizeof(float) * p->batch, hipMemcpyDeviceToDevice, s));
     p->mu_valid = true;
   }
-  STCHK(prologue_from_state(p, mu_in_use(p, mu)));
+  // (the whole-image-in-LDS kernel starts from the state itself; the
+  // spectra of the prologue serve the two-pass kernels and the warm start)
+  if (!p->small || p->opt.warm_iters > 0) STCHK(prologue_from_state(p, mu_in_use(p, mu)));
   if (p->opt.warm_iters > 0) STCHK(warm_start(p, mask, lambda, mu));
   if (p->small) STCHK(iterate_small(p, mask, lambda, mu, iters, x_out));
   else STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
@@ -1689,7 +1693,7 @@ extern "C" deconv_status deconv_admm_continue(deconv_plan p, const float* lambda
     HIPCHK(hipMemcpyAsync(p->mu_cur, mu, sizeof(float) * p->batch, hipMemcpyDeviceToDevice, p->stream));
     p->mu_valid = true;
   }
-  STCHK(prologue_from_state(p, mu_in_use(p, mu)));
+  if (!p->small) STCHK(prologue_from_state(p, mu_in_use(p, mu)));
   if (p->small) STCHK(iterate_small(p, p->mask, lambda, mu, iters, x_out));
   else STCHK(iterate(p, p->mask, lambda, mu, iters, x_out, false));
   return finish(p, iters, ytilde_out, stats, mu_in_use(p, mu));

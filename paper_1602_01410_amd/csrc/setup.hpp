@@ -279,21 +279,22 @@ __device__ __forceinline__ float init_value(const ImgMeta& mt, const float* __re
   return observed(mt, mask, si, sj) ? y[mt.px + (long long)si * mt.n + sj] : mean;
 }
 
-// ytilde^0, v^0 = D ytilde^0, d^0 = 0 (blocks of rows; mean from the partials)
+// ytilde^0, v^0 = D ytilde^0, d^0 = 0 (one row per block and step; every
+// block sums the partials of the observed mean in the same order)
 __global__ void __launch_bounds__(kNT) init_state_kernel(const ImgMeta* meta, const float* __restrict__ y,
                                                         const uint8_t* __restrict__ mask, const double* part,
                                                         int nparts, float* yt, float2* v, float2* d) {
   const int img = blockIdx.y;
   const ImgMeta mt = meta[img];
   __shared__ float smean;
-  if (threadIdx.x == 0) {
-    double s = 0.0, c = 0.0;
-    for (int k = 0; k < nparts; ++k) {
-      s += part[2 * ((long long)img * nparts + k)];
-      c += part[2 * ((long long)img * nparts + k) + 1];
-    }
-    smean = c > 0 ? (float)(s / c) : 0.f;
+  __shared__ double red[3 * (kNT / 64)];
+  double s = 0.0, c = 0.0, dummy = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kNT) {
+    s += part[2 * ((long long)img * nparts + k)];
+    c += part[2 * ((long long)img * nparts + k) + 1];
   }
+  block_sum3(s, c, dummy, red);
+  if (threadIdx.x == 0) smean = c > 0 ? (float)(s / c) : 0.f;
   __syncthreads();
   const float mn = smean;
   for (int i = blockIdx.x; i < mt.m; i += gridDim.x) {
