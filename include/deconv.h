@@ -306,7 +306,9 @@ deconv_status deconv_plan_bwd_kernel_times(deconv_plan p, double* out);
 
 /* Launch shapes in use (after autotuning): out[0] = row pass, out[1] =
    column pass, each 1 (one launch per line length), 2 (one launch for all
-   lengths) or 3 (hybrid, see deconv_options.schedule).  Host call. */
+   lengths) or 3 (hybrid, see deconv_options.schedule).  On the
+   whole-image-in-LDS path these are the shapes of the two-pass kernels that
+   a warm start runs.  Host call. */
 deconv_status deconv_plan_schedule(deconv_plan p, int32_t* out);
 
 /* Tile knobs in use (after autotuning), host call: out[0] = row tile
