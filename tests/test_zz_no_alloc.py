@@ -15,19 +15,20 @@ pytestmark = pytest.mark.gpu
 OPTS = dict(schedule=3, check_every=10)
 
 
-def _compare(probs, iters):
+def _compare(probs, iters, **extra):
     import torch
     from paper_1602_01410_amd import binding
+    opts = dict(OPTS, **extra)
     images = [desc(p) for p in probs]
     y, mask, h, lam, mu = device_inputs(probs)
-    plan = binding.Plan(images, **OPTS)
+    plan = binding.Plan(images, **opts)
     yt_ref = torch.empty_like(y)
     x_ref, st_ref = plan.run(y, mask, h, lam, mu, iters, ytilde_out=yt_ref, stats=True)
     torch.cuda.synchronize()
     plan.close()
     x = torch.full_like(y, float("nan"))
     yt = torch.full_like(y, float("nan"))
-    x, st = binding.run_static(images, y, mask, h, lam, mu, iters, x_out=x, ytilde_out=yt, stats=True, **OPTS)
+    x, st = binding.run_static(images, y, mask, h, lam, mu, iters, x_out=x, ytilde_out=yt, stats=True, **opts)
     torch.cuda.synchronize()
     log("  %d images, %d px: max |dx| %.3e" % (len(probs), y.numel(), float((x - x_ref).abs().max())))
     assert torch.equal(x, x_ref)
@@ -45,8 +46,10 @@ def test_static_run_matches_plan_run_twice():
     small = [synth.config_plain_72()]
     log("first call: 3 images")
     _compare(big, 30)
-    log("second call: one 72^2 image")
+    log("second call: one 72^2 image (whole-image-in-LDS path)")
     _compare(small, 25)
+    log("third call: the same on the two-pass kernels")
+    _compare(small, 25, small_images=0)
 
 
 def test_static_run_refuses_a_batch_beyond_the_array():
