@@ -276,11 +276,14 @@ deconv_status deconv_admm_backward(deconv_plan p, const float* y, const uint8_t*
 deconv_status deconv_plan_run_id(deconv_plan p, uint64_t* out);
 
 /* Blur spectrum H^ = DFT2(h embedded circularly centred at the origin) for
-   every image (device float2 packed, full height x width per image), computed
-   as the plan's runs compute the half of it the passes read: by direct sums
-   over the taps (FP32, one launch for the batch) when every kernel has at
-   most 65 taps a side, else with the library's own FFT.  Synchronous.  The
-   plan's own blur spectrum, state and checkpoints are left as they were. */
+   every image (device float2 packed, full height x width per image): by
+   direct sums over the taps (FP32, one launch for the batch) when every
+   kernel has at most 65 taps a side, else with the library's own FFT, as the
+   plan's runs compute the half of it they read (except that for a kernel
+   taken as separable, see separable_blur, a run forms it as the product of
+   the two 1-D spectra, equal to within about 1e-6 relative).  Synchronous.
+   The plan's own blur spectrum, state and checkpoints are left as they
+   were. */
 deconv_status deconv_blur_spectrum(deconv_plan p, const float* h, float* spectrum_out);
 
 /* Batched 2-D complex DFT with the library's FFT (unnormalised; inverse = 1

@@ -901,17 +901,27 @@ static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* ful
     maxm = std::max(maxm, m.m);
   }
   const int rowblk = (maxm + kBlurRows - 1) / kBlurRows;
+  // the separable factors (and flags) of every image: the column pass reads
+  // them, and the half spectrum of a separable blur is their product
+  auto separable = [&]() -> deconv_status {
+    hipLaunchKernelGGL(separable_psf_kernel, dim3((maxout + kNT - 1) / kNT, B), dim3(kNT), 0, s, p->d_meta, h,
+                       p->hoff, p->tw, p->hsep, p->sep, p->opt.separable_blur);
+    HIPCHK(hipGetLastError());
+    return DECONV_OK;
+  };
   if (maxk <= kBlurMaxK) {
     if (full_out) {
       int maxn = 0;
       for (const ImgMeta& m : p->meta) maxn = std::max(maxn, m.n);
       hipLaunchKernelGGL(blur_half_kernel, dim3((maxn + kBlurCols - 1) / kBlurCols, rowblk, B), dim3(kNT), 0, s,
-                         p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, reinterpret_cast<float2*>(full_out));
+                         p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, reinterpret_cast<float2*>(full_out),
+                         nullptr, nullptr);
       HIPCHK(hipGetLastError());
     }
     if (pack) {
+      STCHK(separable());
       hipLaunchKernelGGL(blur_half_kernel, dim3((maxcol + kBlurCols - 1) / kBlurCols, rowblk, B), dim3(kNT), 0, s,
-                         p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, nullptr);
+                         p->d_meta, h, p->hoff, p->tw, p->hh, p->hsum, nullptr, p->hsep, p->sep);
       HIPCHK(hipGetLastError());
     }
   } else {
@@ -934,12 +944,8 @@ static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* ful
     if (pack) {
       hipLaunchKernelGGL(pack_half_kernel, dim3(gx, B), dim3(kNT), 0, s, p->d_meta, grid, p->goff, p->hh);
       HIPCHK(hipGetLastError());
+      STCHK(separable());
     }
-  }
-  if (pack) {
-    hipLaunchKernelGGL(separable_psf_kernel, dim3((maxout + kNT - 1) / kNT, B), dim3(kNT), 0, s, p->d_meta, h,
-                       p->hoff, p->tw, p->hsep, p->sep, p->opt.separable_blur);
-    HIPCHK(hipGetLastError());
   }
   std::vector<float2> hs(B);
   HIPCHK(hipMemcpyAsync(hs.data(), p->hsum, sizeof(float2) * B, hipMemcpyDeviceToHost, s));
@@ -1539,8 +1545,9 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
 }
 
 // Iterations on the whole-image-in-LDS path: one launch per check period (or
-// per kSmallChunk iterations without checks), each followed by the residual
-// kernel when its last iteration is a check.  d stays in its buffer.
+// per kSmallChunk iterations without checks); a launch whose last iteration
+// is a check records the residuals and the stop decisions itself (each
+// workgroup holds a whole image).  d stays in its buffer.
 constexpr int kSmallChunk = 50;
 
 static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
@@ -1562,9 +1569,15 @@ static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const 
     a.lam = lam;
     a.mu = mu;
     a.tw = p->tw;
-    a.partials = p->partials;
     a.done = p->done;
     a.x_out = x_out;
+    a.res = p->res;
+    a.nonfinite = p->nonfinite;
+    a.iters_done = p->iters_done;
+    a.stop_buf = p->stop_buf;
+    a.tol_p = p->opt.tol_primal;
+    a.tol_d = p->opt.tol_dual;
+    a.cur_d = p->cur_d;
     a.iters = cnt;
     a.check = K > 0 && (it + cnt) % K == 0;
     a.store_x = it + cnt == iters || (a.check && stopping);
@@ -1578,10 +1591,6 @@ static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const 
     timer.done();
     it += cnt;
     if (a.check) {
-      hipLaunchKernelGGL(residual_kernel, dim3(p->batch), dim3(kNT), 0, s, p->d_meta, p->partials, p->res, p->done,
-                         p->nonfinite, p->iters_done, cnt, 1, p->opt.tol_primal, p->opt.tol_dual, 0.0, p->mu_cur,
-                         p->dscale, p->stop_buf, p->cur_d);
-      HIPCHK(hipGetLastError());
       if (stopping) {
         std::vector<int> dn(p->batch);
         HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * p->batch, hipMemcpyDeviceToHost, s));

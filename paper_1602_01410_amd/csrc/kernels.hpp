@@ -388,6 +388,28 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
   }
 }
 
+// Record one image's residuals from the sums over its pixels (a = |d'-d|^2,
+// b = |v'-v|^2, c = |z'-z|^2); with stop_test, set the stop flag when both
+// tolerances hold (scaled by sqrt(2 m' n'), the size of v).  Returns true
+// when the image is or becomes stopped.
+__device__ __forceinline__ bool record_residuals(const ImgMeta& mt, int img, double a, double b, double c,
+                                                 double* res, int* done, int* nonfinite, int* iters_done,
+                                                 int iters_since, int stop_test, double tol_p, double tol_d,
+                                                 int* stop_buf, int cur_d) {
+  if (done && done[img]) return true;
+  const double nd = sqrt(a), nv = sqrt(b);
+  res[3 * img] = nd; res[3 * img + 1] = nv; res[3 * img + 2] = sqrt(c);
+  if (!isfinite(a) || !isfinite(b) || !isfinite(c)) nonfinite[img] = 1;
+  iters_done[img] += iters_since;
+  const double sc = sqrt(2.0 * (double)mt.m * (double)mt.n);
+  if (stop_test && done && (tol_p > 0 || tol_d > 0) && nd <= tol_p * sc && nv <= tol_d * sc) {
+    done[img] = 1;   // a stopped image keeps its penalty and its d (in buffer cur_d)
+    stop_buf[img] = cur_d;
+    return true;
+  }
+  return false;
+}
+
 // ---------------------------------------------------------------------------
 // row pass
 // ---------------------------------------------------------------------------

@@ -93,9 +93,13 @@ __global__ void embed_psf_kernel(const ImgMeta* meta, const float* __restrict__ 
 constexpr int kBlurCols = 32;
 constexpr int kBlurRows = 64;
 constexpr int kBlurMaxK = 65;
+// With sep (nullable; half spectrum only) an image whose sep flag is set
+// takes H(ky, kx) = U(ky) V(kx) from its 1-D spectra in hsep (written by
+// separable_psf_kernel beforehand) instead of the sums over its taps.
 __global__ void __launch_bounds__(kNT) blur_half_kernel(const ImgMeta* meta, const float* __restrict__ h,
                                                        const long long* hoff, const float2* __restrict__ tw,
-                                                       float2* hh, float2* hsum, float2* full) {
+                                                       float2* hh, float2* hsum, float2* full,
+                                                       const float2* hsep, const int* sep) {
   const int img = blockIdx.z;
   const ImgMeta mt = meta[img];
   const int ncol = full ? mt.n : mt.nb * mt.C;
@@ -104,6 +108,18 @@ __global__ void __launch_bounds__(kNT) blur_half_kernel(const ImgMeta* meta, con
   const int ky0 = blockIdx.y * kBlurRows;
   if (kx0 >= ncol || ky0 >= mt.m) return;
   const int nrow = min(kBlurRows, mt.m - ky0);
+  if (!full && sep && sep[img]) {
+    const float2* __restrict__ U = hsep + mt.tab;
+    const float2* __restrict__ V = U + mt.m;
+    for (int t = threadIdx.x; t < nrow * kBlurCols; t += kNT) {
+      const int ky = ky0 + t / kBlurCols, kx = kx0 + t % kBlurCols;
+      if (kx >= ncol) continue;
+      const float2 H = kx < nval ? cmul(U[ky], V[kx]) : make_float2(0.f, 0.f);
+      hh[mt.hh + ((long long)(kx >> mt.logC) * mt.m + ky) * mt.C + (kx & (mt.C - 1))] = H;
+      if (kx == 0 && ky == 0) hsum[img] = H;
+    }
+    return;
+  }
   const int b = mt.b, K = 2 * b + 1;
   const float* __restrict__ hk = h + hoff[img];
   const float2* __restrict__ twn = tw + mt.twr;
@@ -343,17 +359,10 @@ __global__ void __launch_bounds__(kNT) residual_kernel(const ImgMeta* meta, cons
   __shared__ double red[3 * (kNT / 64)];
   block_sum3(a, b, c, red);
   if (threadIdx.x == 0) {
-    if (done && done[img]) return;
-    const double nd = sqrt(a), nv = sqrt(b);
-    res[3 * img] = nd; res[3 * img + 1] = nv; res[3 * img + 2] = sqrt(c);
-    if (!isfinite(a) || !isfinite(b) || !isfinite(c)) nonfinite[img] = 1;
-    iters_done[img] += iters_since;
-    const double sc = sqrt(2.0 * (double)mt.m * (double)mt.n);
-    if (stop_test && done && (tol_p > 0 || tol_d > 0) && nd <= tol_p * sc && nv <= tol_d * sc) {
-      done[img] = 1;   // a stopped image keeps its penalty and its d (in buffer cur_d)
-      stop_buf[img] = cur_d;
+    if (record_residuals(mt, img, a, b, c, res, done, nonfinite, iters_done, iters_since, stop_test, tol_p, tol_d,
+                         stop_buf, cur_d))
       return;
-    }
+    const double nd = sqrt(a), nv = sqrt(b);
     if (adapt_t > 0) {
       float f = 1.f;
       if (nd > adapt_t * nv) { mu_cur[img] *= 2.f; f = 0.5f; }

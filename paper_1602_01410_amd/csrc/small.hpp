@@ -36,11 +36,19 @@ struct SmallArgs {
   const float* lam;
   const float* mu;
   const float2* tw;
-  double* partials;          // 3 per row tile of the image: written at slot rt0 (rest 0)
-  const int* done;
+  int* done;                 // per image: stop flag (read at the start, set by a check)
   float* x_out;
+  // a check (the workgroup holds the whole image, so it finishes the
+  // residuals itself): per image |d'-d|, |v'-v|, |z'-z|, the non-finite
+  // flag, iterations done, the d buffer of a stop
+  double* res;
+  int* nonfinite;
+  int* iters_done;
+  int* stop_buf;
+  double tol_p, tol_d;
+  int cur_d;
   int iters;                 // iterations of this launch
-  int check;                 // 1: residuals of the last iteration into the partials
+  int check;                 // 1: residuals of the last iteration (and the stop test)
   int store_x;               // 1: x of the last iteration into x_out
   float alpha;
 };
@@ -343,12 +351,9 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
     __shared__ double red[3 * (kNTS / 64)];
     double s0 = rd, s1 = rv, s2 = rz;
     block_sum3(s0, s1, s2, red);
-    for (int t = (int)threadIdx.x; t < mt.nrt; t += kNTS) {
-      double* out = a.partials + 3 * (mt.rt0 + t);
-      out[0] = t == 0 ? s0 : 0.0;
-      out[1] = t == 0 ? s1 : 0.0;
-      out[2] = t == 0 ? s2 : 0.0;
-    }
+    if (threadIdx.x == 0)
+      record_residuals(mt, img, s0, s1, s2, a.res, a.done, a.nonfinite, a.iters_done, a.iters, 1, a.tol_p,
+                       a.tol_d, a.stop_buf, a.cur_d);
   }
 }
 
