@@ -204,8 +204,12 @@ deconv_status deconv_plan_destroy(deconv_plan p);
  *   mask   device uint8, packed images, 1 = observed; read only for images of
  *          kind DECONV_MASK_EXPLICIT (may be NULL if there are none)
  *   h      device float, packed kernels (convolution, centre (b, b)); each
- *          must have a non-zero sum (else DECONV_ERR_SINGULAR, checked on the
- *          host after the spectrum is built; the call then synchronises)
+ *          must have a non-zero sum, else DECONV_ERR_SINGULAR.  The host
+ *          checks the sums once the run's work is queued (waiting only for
+ *          the spectrum setup; plans given a workspace wait for it before
+ *          queuing the iterations); on DECONV_ERR_SINGULAR the call returns
+ *          after the queued work has finished and the outputs and the
+ *          plan's state are unspecified
  *   lambda device float [batch], >= 0 (TV weight)
  *   mu     device float [batch], > 0 (ADMM penalty)
  *   iters  >= 1

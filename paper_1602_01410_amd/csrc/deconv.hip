@@ -225,6 +225,11 @@ struct deconv_plan_s {
   long long* goff = nullptr;
   long long* hoff = nullptr;
   float2* hsum = nullptr;     // DC term of each spectrum (host check)
+  // plans that allocate their own memory: the DC terms come back through
+  // pinned memory, checked once the run's work is queued (hsum_ev)
+  float2* hsum_host = nullptr;
+  hipEvent_t hsum_ev = nullptr;
+  bool hsum_pending = false;
   float* mu_cur = nullptr;    // adaptive penalty: current mu per image
   float* dscale = nullptr;    // adaptive penalty: rescale of d per image
   // whole-image-in-LDS path: image indices grouped by side, one launch per
@@ -681,6 +686,7 @@ extern "C" deconv_status deconv_plan_workspace_size(int32_t batch, const deconv_
 
 extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
   if (!p) return DECONV_ERR_INVALID_ARG;
+  if (p->hsum_pending) (void)hipEventSynchronize(p->hsum_ev);   // a copy into hsum_host in flight
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto st : p->side) (void)hipStreamDestroy(st);
@@ -693,6 +699,8 @@ extern "C" deconv_status deconv_plan_destroy(deconv_plan p) {
   for (auto& kv : p->bwd_graphs) (void)hipGraphExecDestroy(kv.second.first);
   for (auto& e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->own_ws && p->ws) (void)hipFree(p->ws);
+  if (p->hsum_host) (void)hipHostFree(p->hsum_host);
+  if (p->hsum_ev) (void)hipEventDestroy(p->hsum_ev);
   delete p;
   return DECONV_OK;
 }
@@ -725,6 +733,12 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   } else {
     if (hipMalloc(&p->ws, lay.total) != hipSuccess) { delete p; return DECONV_ERR_OOM; }
     p->own_ws = true;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->hsum_host), sizeof(float2) * batch, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&p->hsum_ev, hipEventDisableTiming) != hipSuccess) {
+      deconv_plan_destroy(p);
+      return DECONV_ERR_HIP;
+    }
   }
   p->ws_bytes = lay.total;
   void* w = p->ws;
@@ -890,8 +904,15 @@ static uint64_t new_run_id() { return ++g_run_id; }
 // rebuilt by every prologue): full_out = the whole spectra (for
 // deconv_blur_spectrum); pack = the half spectrum the passes read and the
 // separable factors (deconv_blur_spectrum leaves them alone)
-static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out, bool pack = true) {
+static bool singular_dc(float2 v) { return !(std::isfinite(v.x) && std::isfinite(v.y)) || (v.x == 0.f && v.y == 0.f); }
+
+// With defer (and pinned memory), the DC terms are copied back without
+// waiting: check_spectrum tests them once the caller has queued the rest of
+// the run, so that the queue never drains between runs.
+static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* full_out, bool pack = true,
+                                    bool defer = false) {
   hipStream_t s = p->stream;
+  p->hsum_pending = false;
   const int B = p->batch;
   int maxk = 0, maxcol = 0, maxout = 0, maxm = 0;
   for (const ImgMeta& m : p->meta) {
@@ -947,12 +968,31 @@ static deconv_status setup_spectrum(deconv_plan_s* p, const float* h, float* ful
       STCHK(separable());
     }
   }
+  if (defer && p->hsum_host) {
+    HIPCHK(hipMemcpyAsync(p->hsum_host, p->hsum, sizeof(float2) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(p->hsum_ev, s));
+    p->hsum_pending = true;
+    return DECONV_OK;
+  }
   std::vector<float2> hs(B);
   HIPCHK(hipMemcpyAsync(hs.data(), p->hsum, sizeof(float2) * B, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < B; ++b)
-    if (!(std::isfinite(hs[b].x) && std::isfinite(hs[b].y)) || (hs[b].x == 0.f && hs[b].y == 0.f))
+    if (singular_dc(hs[b])) return DECONV_ERR_SINGULAR;
+  return DECONV_OK;
+}
+
+// the deferred DC-term test; a singular blur fails the call after the work
+// queued on it has finished (its outputs are then undefined)
+static deconv_status check_spectrum(deconv_plan_s* p) {
+  if (!p->hsum_pending) return DECONV_OK;
+  p->hsum_pending = false;
+  HIPCHK(hipEventSynchronize(p->hsum_ev));
+  for (int b = 0; b < p->batch; ++b)
+    if (singular_dc(p->hsum_host[b])) {
+      HIPCHK(hipStreamSynchronize(p->stream));
       return DECONV_ERR_SINGULAR;
+    }
   return DECONV_OK;
 }
 
@@ -1466,6 +1506,10 @@ static deconv_status copy_ckpt(deconv_plan_s* p, int slot, bool to_store) {
 
 // iterations per replayed graph when residuals are never checked
 constexpr int kGraphChunk = 10;
+// without a stop test the host reads nothing between check periods, so one
+// graph holds several (up to this many iterations): each graph launch costs
+// the queue a gap of several microseconds
+constexpr int kGraphIters = 50;
 
 // iterate from the current spectra; handles checkpoints, graphs, stopping
 static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
@@ -1481,9 +1525,15 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
   int it = 0;
   while (it < iters) {
     // graph replay of whole check periods (no checkpoint inside, not the
-    // last); without checks, of chunks of kGraphChunk iterations
-    const int G = K > 0 ? K : kGraphChunk;
-    if (p->opt.use_graph && ck == 0 && it % G == 0 && it + G < iters) {
+    // last); without checks, of chunks of kGraphChunk iterations; without a
+    // stop test, of as many periods as fit in kGraphIters iterations
+    const int G0 = K > 0 ? K : kGraphChunk;
+    int G = G0;
+    if (!stopping) {
+      G = G0 * std::max(1, kGraphIters / G0);
+      while (G > G0 && it + G >= iters) G -= G0;
+    }
+    if (p->opt.use_graph && ck == 0 && it % G0 == 0 && it + G < iters) {
       const int cur0 = p->cur_d;
       std::vector<uintptr_t> key = {(uintptr_t)G, (uintptr_t)cur0, (uintptr_t)mask, (uintptr_t)lam,
                                     (uintptr_t)mu, (uintptr_t)x_out};
@@ -1661,7 +1711,7 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   p->ck_valid = false;
   p->run_id = 0;
   p->mask = mask;
-  STCHK(setup_spectrum(p, h, nullptr));
+  STCHK(setup_spectrum(p, h, nullptr, true, true));
   STCHK(reset_counters(p));
   hipLaunchKernelGGL(observed_sum_kernel, dim3(kMeanBlocks, p->batch), dim3(kNT), 0, s, p->d_meta, y, mask,
                      p->mean);
@@ -1680,6 +1730,7 @@ extern "C" deconv_status deconv_admm_run(deconv_plan p, const float* y, const ui
   if (p->opt.warm_iters > 0) STCHK(warm_start(p, mask, lambda, mu));
   if (p->small) STCHK(iterate_small(p, mask, lambda, mu, iters, x_out));
   else STCHK(iterate(p, mask, lambda, mu, iters, x_out, ckpt));
+  STCHK(check_spectrum(p));
   p->have_state = true;
   p->last_iters = iters;
   p->ck_valid = ckpt;
