@@ -437,6 +437,7 @@ static void build_layout(deconv_plan_s* p, Layout& lay) {
   lay.off_tab = take(sizeof(float) * tab);
   lay.off_tw = take(sizeof(float2) * tw);
   lay.off_part = take(sizeof(double) * 3 * rt);
+  // done .. res back to back: reset_counters clears them with one fill
   lay.off_done = take(sizeof(int) * B);
   lay.off_nonf = take(sizeof(int) * B);
   lay.off_itd = take(sizeof(int) * B);
@@ -1509,7 +1510,7 @@ constexpr int kGraphChunk = 10;
 // without a stop test the host reads nothing between check periods, so one
 // graph holds several (up to this many iterations): each graph launch costs
 // the queue a gap of several microseconds
-constexpr int kGraphIters = 50;
+constexpr int kGraphIters = 250;
 
 // iterate from the current spectra; handles checkpoints, graphs, stopping
 static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
@@ -1684,12 +1685,13 @@ static deconv_status finish(deconv_plan_s* p, int iters, float* ytilde_out, deco
 }
 
 static deconv_status reset_counters(deconv_plan_s* p) {
-  hipStream_t s = p->stream;
-  const int B = p->batch;
-  HIPCHK(hipMemsetAsync(p->done, 0, sizeof(int) * B, s));
-  HIPCHK(hipMemsetAsync(p->nonfinite, 0, sizeof(int) * B, s));
-  HIPCHK(hipMemsetAsync(p->iters_done, 0, sizeof(int) * B, s));
-  HIPCHK(hipMemsetAsync(p->res, 0, sizeof(double) * 3 * B, s));
+  // done, nonfinite, iters_done, stop_buf and res lie back to back in the
+  // workspace (build_layout): one fill
+  const long long words = (reinterpret_cast<const char*>(p->res + 3 * p->batch) -
+                           reinterpret_cast<const char*>(p->done)) / 4;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)std::min<long long>((words + kNT - 1) / kNT, 64)), dim3(kNT),
+                     0, p->stream, reinterpret_cast<unsigned*>(p->done), words);
+  HIPCHK(hipGetLastError());
   return DECONV_OK;
 }
 
