@@ -240,18 +240,18 @@ def pass_roofline(problems, inputs, iters, check_every, unobs, name):
     small = pplan.tiles()[3] == 1
     pplan.close()
     if small:
-        # whole-image-in-LDS path: one launch per check period reads and
-        # writes the state once (ytilde 4, v 8, d 8 each way per pixel) and
-        # reads the blur half spectrum (8 per entry); x (4) on the last
+        # whole-image-in-LDS path: one launch reads and writes the state once
+        # (ytilde 4, v 8, d 8 each way per pixel) and reads the blur half
+        # spectrum (8 per entry); x (4) on the last
         avg = row_ms / max(row_n, 1)
         ab = sum(40.0 * p["M"] * p["N"] + 8.0 * p["M"] * (p["N"] // 2 + 1) for p in problems)
         log("whole-image-in-LDS launch %.2f us x %d" % (avg * 1e3, row_n))
         return {"bound": "hbm", "achieved": round(ab / (avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ab / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None, "traffic_frac": None,
                 "kernel": "small_kernel", "launch_us": round(avg * 1e3, 2), "alg_bytes_per_launch": int(ab),
-                "iters_per_launch": check_every or 50,
-                "note": "the image stays in LDS for a whole check period; LDS traffic and workgroup barriers, "
-                        "not HBM, bound this path"}
+                "iters_per_launch": round(iters / max(row_n, 1), 1),
+                "note": "the image stays in LDS for a whole launch (up to 200 iterations, a check every "
+                        "check_every); one compute unit's VALU and LDS, not HBM, bound this path"}
     rb, cb = alg_bytes(problems, unobs)
     row_avg, col_avg = row_ms / max(row_n, 1), col_ms / max(col_n, 1)
     log("row pass %.2f us x %d, column pass %.2f us x %d" % (row_avg * 1e3, row_n, col_avg * 1e3, col_n))

@@ -149,9 +149,9 @@ typedef struct {
   int32_t small_images; /* Plans whose images are all square with a side
                            of 32, 48, 64, 72 or 96 and that use one BGS pass,
                            a fixed penalty, grey images and no checkpoints
-                           can run every iteration of a check period in one
-                           workgroup per image, the image held in LDS (one
-                           launch per check period instead of two per
+                           can run up to 200 iterations (one check period
+                           with tolerances) in one workgroup per image, the
+                           image held in LDS (one launch instead of two per
                            iteration).  2 (default): such plans whose sides
                            are all at most 72 take it (on MI355X it is 1.1x
                            to 2.4x as fast there; one 96^2 image is faster
@@ -302,7 +302,7 @@ deconv_status deconv_fft2(int32_t count, int32_t height, int32_t width, float* d
    out[2] = column-pass milliseconds, out[3] = column-pass launches.
    Passes replayed inside a graph are not bracketed.  On the
    whole-image-in-LDS path (deconv_plan_tiles out[3] = 1) out[0..1] count
-   its launches (one per check period) and out[2..3] are 0. */
+   its launches (up to 200 iterations each) and out[2..3] are 0. */
 deconv_status deconv_plan_kernel_times(deconv_plan p, double* out);
 
 /* As deconv_plan_kernel_times for the passes of the reverse pass

@@ -1595,11 +1595,14 @@ static deconv_status iterate(deconv_plan_s* p, const uint8_t* mask, const float*
   return DECONV_OK;
 }
 
-// Iterations on the whole-image-in-LDS path: one launch per check period (or
-// per kSmallChunk iterations without checks); a launch whose last iteration
-// is a check records the residuals and the stop decisions itself (each
-// workgroup holds a whole image).  d stays in its buffer.
+// Iterations on the whole-image-in-LDS path: one launch per check period
+// when a stop test needs the host between periods, else per kSmallIters
+// iterations (several check periods; kSmallChunk without checks).  The
+// kernel records the residuals of every check in its launch (each
+// workgroup holds a whole image) and the stop decisions.  d stays in its
+// buffer.
 constexpr int kSmallChunk = 50;
+constexpr int kSmallIters = 200;
 
 static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const float* lam, const float* mu,
                                    int iters, float* x_out) {
@@ -1607,8 +1610,10 @@ static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const 
   const int K = p->opt.check_every;
   const bool stopping = K > 0 && (p->opt.tol_primal > 0 || p->opt.tol_dual > 0);
   int it = 0;
+  // launches start at check-period boundaries
+  const int span = K > 0 ? (stopping ? K : K * std::max(1, kSmallIters / K)) : kSmallChunk;
   while (it < iters) {
-    const int cnt = std::min(K > 0 ? K - it % K : kSmallChunk, iters - it);
+    const int cnt = std::min(span, iters - it);
     SmallArgs a{};
     a.meta = p->d_meta;
     a.yt = p->yt;
@@ -1630,8 +1635,10 @@ static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const 
     a.tol_d = p->opt.tol_dual;
     a.cur_d = p->cur_d;
     a.iters = cnt;
-    a.check = K > 0 && (it + cnt) % K == 0;
-    a.store_x = it + cnt == iters || (a.check && stopping);
+    a.check_every = K;
+    a.stop_test = stopping;
+    const bool checked = K > 0 && cnt % K == 0;   // the launch ends with a check
+    a.store_x = it + cnt == iters || (checked && stopping);
     a.alpha = p->opt.alpha;
     PassTimer timer(p, &p->ev_row);
     for (size_t q = 0; q < p->small_groups.size(); ++q) {
@@ -1641,7 +1648,7 @@ static deconv_status iterate_small(deconv_plan_s* p, const uint8_t* mask, const 
     }
     timer.done();
     it += cnt;
-    if (a.check) {
+    if (checked) {
       if (stopping) {
         std::vector<int> dn(p->batch);
         HIPCHK(hipMemcpyAsync(dn.data(), p->done, sizeof(int) * p->batch, hipMemcpyDeviceToHost, s));

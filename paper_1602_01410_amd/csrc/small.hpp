@@ -48,7 +48,8 @@ struct SmallArgs {
   double tol_p, tol_d;
   int cur_d;
   int iters;                 // iterations of this launch
-  int check;                 // 1: residuals of the last iteration (and the stop test)
+  int check_every;           // residuals after every check_every-th iteration of the launch (0: none)
+  int stop_test;             // 1: apply the tolerances at those checks
   int store_x;               // 1: x of the last iteration into x_out
   float alpha;
 };
@@ -234,7 +235,7 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
 
   for (int it = 0; it < a.iters; ++it) {
     const bool last = it + 1 == a.iters;
-    const bool chk = last && a.check;
+    const bool chk = a.check_every > 0 && (it + 1) % a.check_every == 0;
     // the offsets and the thread index made opaque per iteration: addresses
     // derived from them are formed where they are used rather than kept in
     // registers across the loop
@@ -334,6 +335,17 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
       }
       if (k % 2 == 1) small_group_fence();
     }
+    if (chk) {
+      // a check: the workgroup holds the whole image, so it records the
+      // image's residuals (and the stop decision) itself
+      __shared__ double red[3 * (kNTS / 64)];
+      double s0 = rd, s1 = rv, s2 = rz;
+      block_sum3(s0, s1, s2, red);
+      if (threadIdx.x == 0)
+        record_residuals(mt, img, s0, s1, s2, a.res, a.done, a.nonfinite, a.iters_done, a.check_every, a.stop_test,
+                         a.tol_p, a.tol_d, a.stop_buf, a.cur_d);
+      rd = rv = rz = 0.f;
+    }
   }
   // the state back to HBM (v was written by the last iteration); the
   // addresses computed here, not kept live through the loop
@@ -346,14 +358,6 @@ __device__ __forceinline__ void small_image(const SmallArgs& a, int img, float2*
       yt[p] = yv[k];
       dg[p] = dv[k];
     }
-  }
-  if (a.check) {
-    __shared__ double red[3 * (kNTS / 64)];
-    double s0 = rd, s1 = rv, s2 = rz;
-    block_sum3(s0, s1, s2, red);
-    if (threadIdx.x == 0)
-      record_residuals(mt, img, s0, s1, s2, a.res, a.done, a.nonfinite, a.iters_done, a.iters, 1, a.tol_p,
-                       a.tol_d, a.stop_buf, a.cur_d);
   }
 }
 
