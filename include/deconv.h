@@ -153,8 +153,8 @@ typedef struct {
                            with tolerances) in one workgroup per image, the
                            image held in LDS (one launch instead of two per
                            iteration).  2 (default): such plans whose sides
-                           are all at most 72 take it (on MI355X it is 1.2x
-                           (72^2) to 2.9x (32^2) as fast there; one 96^2
+                           are all at most 72 take it (on MI355X it is 1.1x
+                           (72^2) to 2.7x (32^2) as fast there; one 96^2
                            image is faster on the two-pass kernels); 1:
                            every such plan takes it; 0: never.  The
                            iterates agree with the two-pass kernels' to

@@ -851,8 +851,8 @@ extern "C" deconv_status deconv_plan_create(deconv_plan* out, int32_t batch, con
   // the options need nothing it lacks (one pass, fixed penalty, grey images,
   // no checkpoints): always with opt.small_images = 1, and with 2 (the
   // default) when no side exceeds kSmallAutoSide (measured on MI355X against
-  // the two-pass kernels: one image of side 32 / 48 / 64 / 72 2.4 / 1.8 /
-  // 1.3 / 1.1x as fast, 64 images of 72^2 1.4x, 256 of 64^2 1.9x; one 96^2
+  // the two-pass kernels: one image of side 32 / 48 / 64 / 72 2.7 / 1.9 /
+  // 1.3 / 1.1x as fast, 64 images of 72^2 1.5x, 256 of 64^2 2.6x; one 96^2
   // image 0.6x)
   p->small = p->opt.small_images != 0 && p->opt.bgs_passes == 1 && !(p->opt.adapt_t > 0) &&
              p->opt.channels == 1 && p->opt.ckpt_every == 0;
