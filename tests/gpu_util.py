@@ -66,7 +66,7 @@ def rel_l2(a, ref):
 
 
 def assert_parity(x, ref, rel=1e-4, absfrac=1e-3, what=""):
-    """Spec bar for an image after N iterations: relative L2 <= rel and
+    """The parity bar for an image after N iterations: relative L2 <= rel and
     max abs error <= absfrac of the reference's dynamic range."""
     r = rel_l2(x, ref)
     rng = float(ref.max() - ref.min())

@@ -84,6 +84,26 @@ def test_default_routing():
     pl.close()
 
 
+@pytest.mark.parametrize("iters,tol,launches", [(200, 0.0, 1), (450, 0.0, 3), (200, 1e-30, 20)])
+def test_launches_per_run(iters, tol, launches):
+    """Without a stop test one launch runs up to 200 iterations (every check
+    inside it recorded); with tolerances, one launch per check period so that
+    the host can stop between them.  The residuals are those of the last
+    check either way."""
+    from paper_1602_01410_amd import binding
+    p = synth.config_plain_72()
+    plan = binding.Plan([desc(p)], check_every=10, profile=1, tol_primal=tol, tol_dual=tol)
+    assert plan.tiles()[3] == 1
+    y, mask, h, lam, mu = device_inputs([p])
+    _, st = plan.run(y, mask, h, lam, mu, iters, stats=True)
+    assert plan.kernel_times()[1] == launches
+    assert st[0]["iters_done"] == iters and st[0]["status"] == 0
+    r = oracle_run(p, iters)
+    assert st[0]["r_primal"] == pytest.approx(r["hist"][-1][0], rel=1e-3)
+    assert st[0]["r_dual"] == pytest.approx(r["hist"][-1][1], rel=1e-3)
+    plan.close()
+
+
 def test_early_stop_and_continue():
     import torch
     from paper_1602_01410_amd import binding
